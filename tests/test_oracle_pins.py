@@ -1,0 +1,372 @@
+"""Pins of the CPU oracle against facts fixed outside it (not GPU tests).
+
+Each test names what it pins: published known answers (Philox), the paper's
+worked window example, exact enumeration, closed forms and invariants.
+"""
+import math
+import os
+import shutil
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import exact_dos as X
+
+
+# ---------------------------------------------------------------- Philox (R4)
+def test_philox_known_answers(golden):
+    with open(os.path.join(golden.dir, "philox_kat.txt")) as f:
+        rows = [l.split() for l in f if l.strip() and not l.startswith("#")]
+    assert len(rows) == 3
+    for r in rows:
+        v = [int(x, 16) for x in r]
+        assert O.philox(v[0:4], v[4:6]) == tuple(v[6:10])
+
+
+@pytest.mark.skipif(shutil.which("hipcc") is None, reason="hipcc not available")
+def test_philox_matches_rocrand_host(golden):
+    """rocRAND's Philox4x32-10, built for the host, on 3000 (seed, T, slot, tag) counters."""
+    tmp = tempfile.mkdtemp()
+    exe = os.path.join(tmp, "ref")
+    subprocess.check_call(["hipcc", "-O1", os.path.join(golden.dir, "rocrand_philox_ref.cpp"),
+                           "-o", exe], stderr=subprocess.DEVNULL)
+    rng = np.random.default_rng(7)
+    cases = []
+    for i in range(3000):
+        seed = int(rng.integers(0, 2**63))
+        T = int(rng.integers(0, 2**62)) if i % 2 else int(rng.integers(0, 10**6))
+        cases.append((seed, T, int(rng.integers(0, 2**31)), int(rng.integers(0, 4))))
+    inp = "".join(f"{s} {T} {sl} {tg}\n" for s, T, sl, tg in cases)
+    out = subprocess.run([exe], input=inp, capture_output=True, text=True, check=True).stdout.split("\n")
+    for (seed, T, sl, tg), line in zip(cases, out):
+        ref = tuple(int(x, 16) for x in line.split())
+        got = O.philox([T & 0xFFFFFFFF, T >> 32, sl, tg], [seed & 0xFFFFFFFF, seed >> 32])
+        assert got == ref
+    shutil.rmtree(tmp)
+
+
+# ------------------------------------------------------ acceptance test (R6)
+def test_accept_exact_predicate_vs_mpmath():
+    """accept(delta, u) == [u < 2^53 e^delta] decided at 60 digits, incl. near-ties."""
+    import mpmath as mp
+    mp.mp.dps = 60
+    rng = np.random.default_rng(3)
+    cases = []
+    for _ in range(4000):
+        d = -float(rng.uniform(0, 40)) if rng.random() < 0.9 else -float(rng.uniform(0, 1e-6))
+        d = math.ldexp(round(math.ldexp(d, 30)), -30)        # dyadic, as on the path
+        y = mp.ldexp(mp.exp(mp.mpf(d)), 53)
+        base = int(mp.floor(y))
+        for off in (-3, -1, 0, 1, 2, 5, -20, 20):             # straddle the exact boundary
+            u = base + off
+            if 0 <= u < 2**53:
+                cases.append((d, u, bool(mp.mpf(u) < y)))
+        u = int(rng.integers(0, 2**53))
+        cases.append((d, u, bool(mp.mpf(u) < y)))
+    for d, u, want in cases:
+        assert O.accept(d, u) == want, (d, u)
+    # special cases
+    assert O.accept(0.0, 2**53 - 1) and O.accept(3.5, 2**53 - 1)
+    assert O.accept(-1e5, 0) and not O.accept(-1e5, 1)
+    assert not O.accept(-37.0, 1)        # 2^53 e^-37 ~ 0.77 < 1
+    assert O.accept(-36.0, 1)            # 2^53 e^-36 ~ 2.09 > 1
+
+
+# ---------------------------------------------------------------- layout (R2)
+def test_layout_reproduces_paper_window_counts(golden):
+    """Potts Q=10, width 1000, o = 75%: 77/317/717/1277 pieces (paper Sec. IV.A)."""
+    with open(os.path.join(golden.dir, "paper_windows.txt")) as f:
+        rows = [l.split() for l in f if l.strip() and not l.startswith("#")]
+    for L, pieces, width, on, od in (map(int, r) for r in rows):
+        c = O.make_config("potts", q=10, L=L, n_windows=pieces, overlap=(on, od), m=1)
+        lo, hi = O.layout(c)
+        assert np.all(hi - lo == width)
+        shift = width * (od - on) // od
+        assert np.array_equal(lo, shift * np.arange(pieces))
+        assert hi[-1] == 2 * L * L and lo[0] == 0
+        # one window fewer cannot cover the range at this width and overlap
+        c2 = O.make_config("potts", q=10, L=L, n_windows=pieces - 1, overlap=(on, od), m=1)
+        lo2, hi2 = O.layout(c2)
+        assert (hi2 - lo2)[0] > width
+
+
+def test_layout_properties():
+    rng = np.random.default_rng(11)
+    for _ in range(300):
+        L = int(rng.integers(4, 40)) * 2
+        h = int(rng.integers(1, 40))
+        den = int(rng.integers(2, 9))
+        num = int(rng.integers(0, den))
+        c = O.make_config("ising", L=L, n_windows=h, overlap=(num, den))
+        S = O.n_bins(c) - 1
+        w = (S * den + (den + (h - 1) * (den - num)) - 1) // (den + (h - 1) * (den - num))
+        if h > 1 and w >= S:
+            continue
+        lo, hi = O.layout(c)
+        assert lo[0] == 0 and hi[-1] == S
+        assert np.all(np.diff(lo) >= 0) and len(set(hi - lo)) == 1
+        for a in range(h - 1):
+            shared = hi[a] - lo[a + 1]
+            # overlap >= o up to the one bin lost to flooring the window starts
+            assert (shared + 1) * den >= num * (hi[a] - lo[a])
+
+
+# ------------------------------------------------------------ exact DOS pins
+def test_exact_routes_agree(golden):
+    assert X.brute_force("ising", 2, 4) == golden.counts("ising_q2_L4_counts.txt")
+    assert X.transfer_matrix("ising", 2, 4) == golden.counts("ising_q2_L4_counts.txt")
+    assert X.kaufman_ising(4) == golden.counts("ising_q2_L4_counts.txt")
+    assert X.kaufman_ising(6) == X.transfer_matrix("ising", 2, 6)
+    assert X.kaufman_ising(8) == golden.counts("ising_q2_L8_counts.txt")
+    assert X.brute_force("potts", 3, 3) == golden.counts("potts_q3_L3_counts.txt")
+    assert X.transfer_matrix("potts", 3, 3) == golden.counts("potts_q3_L3_counts.txt")
+
+
+def test_brute_force_small_table():
+    """Ising L=4: the enumeration's counts (2^16 states) at a few levels."""
+    g = X.brute_force("ising", 2, 4)
+    assert g[0] == 2 and g[2] == 32 and g[3] == 64 and g[8] == 20524 and sum(g) == 2**16
+    assert g[1] == 0 and g[15] == 0
+
+
+@pytest.mark.parametrize("L", [16, 24, 32, 48, 64])
+def test_ising_exact_invariants(golden, L):
+    lg = golden.lng(f"ising_L{L}_lng.txt")
+    N = L * L
+    assert len(lg) == N + 1
+    ok = np.isfinite(lg)
+    # sum g = 2^N
+    mx = lg[ok].max()
+    assert abs(mx + math.log(np.exp(lg[ok] - mx).sum()) - N * math.log(2)) < 1e-9 * N
+    # E -> -E symmetry (even L), ground state 2, closed-form low levels 2N, 4N
+    assert np.allclose(lg[ok], lg[::-1][ok], rtol=0, atol=1e-9 * N)
+    assert lg[0] == pytest.approx(math.log(2))
+    assert lg[2] == pytest.approx(math.log(2 * N)) and lg[3] == pytest.approx(math.log(4 * N))
+    assert list(np.where(~ok)[0]) == [1, N - 1]
+
+
+@pytest.mark.parametrize("name,q,L", [("potts_q3_L3_counts.txt", 3, 3), ("potts_q3_L4_counts.txt", 3, 4),
+                                      ("potts_q4_L4_counts.txt", 4, 4), ("potts_q3_L5_counts.txt", 3, 5)])
+def test_potts_exact_closed_forms(golden, name, q, L):
+    g = golden.counts(name)
+    N = L * L
+    assert sum(g) == q**N and g[0] == q and g[4] == q * (q - 1) * N
+    if L >= 4:
+        assert g[6] == 2 * N * q * (q - 1)             # aligned dominoes
+        assert g[7] == 2 * N * q * (q - 1) * (q - 2)   # two different flipped neighbours
+
+
+def test_mask_rule_matches_exact_zero_set(golden):
+    for name, model, q, L in [("ising_q2_L4_counts.txt", "ising", 2, 4),
+                              ("ising_q2_L6_counts.txt", "ising", 2, 6),
+                              ("ising_q2_L8_counts.txt", "ising", 2, 8),
+                              ("potts_q3_L4_counts.txt", "potts", 3, 4),
+                              ("potts_q4_L4_counts.txt", "potts", 4, 4),
+                              ("potts_q3_L5_counts.txt", "potts", 3, 5)]:
+        g = np.array(golden.counts(name), dtype=object)
+        c = O.make_config(model, q=q, L=L)
+        assert np.array_equal(O.mask_rule(c), (g > 0).astype(np.uint8)), name
+    for L in (16, 32):
+        lg = golden.lng(f"ising_L{L}_lng.txt")
+        c = O.make_config("ising", L=L)
+        assert np.array_equal(O.mask_rule(c), np.isfinite(lg).astype(np.uint8))
+
+
+def test_energy_function_vs_broken_bond_count():
+    """orc_energy against the enumeration's independent broken-bond definition."""
+    rng = np.random.default_rng(5)
+    for model, q in (("ising", 2), ("potts", 3), ("potts", 10)):
+        for L in (3, 4, 7, 8):
+            if model == "ising" and L % 2:
+                continue
+            c = O.make_config(model, q=q, L=L)
+            for _ in range(20):
+                s = rng.integers(0, q, size=(L, L)).astype(np.uint8)
+                broken = int((s != np.roll(s, 1, 0)).sum() + (s != np.roll(s, 1, 1)).sum())
+                E = -2 * L * L + (2 * broken if model == "ising" else broken)
+                assert O.energy(c, s.ravel()) == E
+
+
+# ------------------------------------------------------- REWL dynamics pins
+def _slots_energy_consistent(sim):
+    st = sim.state()
+    c = sim.cfg
+    N = c.L * c.L
+    for sl in range(sim.S):
+        E = O.energy(c, st["spins"][sl])
+        b = (E + 2 * N) // 4 if c.model == 0 else E + 2 * N
+        assert b == st["bins"][sl]
+        a = sl // c.walkers_per_window
+        assert sim.lo[a] <= b <= sim.hi[a]
+    return st
+
+
+@pytest.mark.parametrize("model,q,L,h,m", [("ising", 2, 8, 4, 2), ("potts", 3, 4, 3, 4),
+                                           ("potts", 10, 6, 5, 2)])
+def test_running_energy_equals_recomputed(model, q, L, h, m):
+    c = O.make_config(model, q=q, L=L, n_windows=h, m=m, X=500, kfinal=12, seed=9)
+    sim = O.Sim(c)
+    _slots_energy_consistent(sim)
+    for _ in range(30):
+        sim.run(1)
+        _slots_energy_consistent(sim)
+
+
+def test_histogram_count_and_dyadic_exactness():
+    m = 4
+    c = O.make_config("ising", L=8, n_windows=3, m=m, X=1000, kfinal=14, seed=21)
+    sim = O.Sim(c)
+    st = sim.state()
+    since = np.zeros(3, dtype=np.int64)            # intervals since the window's last merge
+    for _ in range(60):
+        k_before = st["k"].copy()
+        sim.run(1)
+        st = sim.state()
+        for a in range(3):
+            since[a] = 0 if st["k"][a] != k_before[a] else since[a] + 1
+            if not st["done"][a]:
+                # H counts every attempt since the merge (one entry per attempt)
+                assert np.all(st["H"][a * m:(a + 1) * m].sum(axis=1) ==
+                              since[a] * c.exchange_interval)
+        # ln g values are multiples of 2^-(k + log2 m): the FP64 path is exact
+        scale = 2.0 ** (st["k"].max() + 2)
+        v = st["lng"] * scale
+        assert np.all(v == np.round(v))
+
+
+def test_thread_count_does_not_change_results():
+    c = O.make_config("potts", q=4, L=6, n_windows=4, m=4, X=2000, kfinal=10, seed=5)
+    a = O.Sim(c)
+    b = O.Sim(c)
+    a.run(25, threads=1)
+    b.run(25, threads=4)
+    sa, sb = a.state(), b.state()
+    for k in sa:
+        assert np.array_equal(np.asarray(sa[k]), np.asarray(sb[k])), k
+
+
+def _stationary(lg_exact, lng_walker, lo, hi, mask):
+    """Expected energy distribution of a walker with fixed weights 1/g_w(E)."""
+    b = np.arange(lo, hi + 1)
+    ok = mask[b] > 0
+    logp = np.where(ok, lg_exact[b] - lng_walker, -np.inf)
+    p = np.exp(logp - logp[ok].max())
+    return p / p.sum()
+
+
+def test_frozen_weights_sample_g_over_gw(golden):
+    """Sweep with fixed ln g_w: visits follow g(E)/g_w(E) over the window (A1/A2)."""
+    lg = X.ln_g(golden.counts("ising_q2_L4_counts.txt"))
+    rng = np.random.default_rng(2)
+    mask = O.mask_rule(O.make_config("ising", L=4))
+    for seed in (100, 101):
+        c = O.make_config("ising", L=4, n_windows=1, m=1, X=1000, k0=39, kfinal=40,
+                          flat=(1, 1), seed=seed)
+        w = np.round(np.where(mask > 0, lg + rng.normal(0, 0.7, size=17), 0.0) * 2**16) / 2**16
+        sim = O.Sim(c, init_lng=w)
+        sim.run(12000)
+        H = sim.state()["H"][0].astype(float)
+        p = _stationary(lg, w, 0, 16, mask)
+        obs = H / H.sum()
+        big = p > 0.02
+        assert np.all(np.abs(obs[big] / p[big] - 1) < 0.05)
+
+
+def test_exchange_keeps_stationary_marginals(golden):
+    """Two windows with different fixed weights, an exchange every 2 attempts.
+
+    Under Eq. (1) the joint law is the product of each walker's g/g_w law, so each
+    walker's visit histogram keeps its single-walker marginal.  The two windows'
+    weights differ inside the overlap, so Eq. (1) is not trivially 1 there.
+    """
+    lg = X.ln_g(golden.counts("ising_q2_L4_counts.txt"))
+    c = O.make_config("ising", L=4, n_windows=2, overlap=(3, 4), m=2, X=2, k0=39, kfinal=40,
+                      flat=(1, 1), seed=31)
+    lo, hi = O.layout(c)
+    mask = O.mask_rule(c)
+    tilt = [0.45 * (np.arange(17) - 8.0), -0.3 * (np.arange(17) - 8.0)]
+    sim = O.Sim(c)
+    tabs = []
+    for a in range(2):
+        t = np.where(mask > 0, lg + tilt[a], 0.0)[lo[a]:hi[a] + 1]
+        t = np.round(t * 2**16) / 2**16
+        sim.set_window_lng(a, t)
+        tabs.append(t)
+    sim.run(400000)
+    st = sim.state()
+    stats = sim.stats()
+    assert stats["ex_acc"][0] > 1000 and stats["ex_acc"][0] < stats["ex_prop"][0]
+    for sl in range(4):
+        a = sl // 2
+        p = _stationary(lg, tabs[a], lo[a], hi[a], mask)
+        H = st["H"][sl].astype(float)
+        obs = H / H.sum()
+        big = p > 0.02
+        assert np.all(np.abs(obs[big] / p[big] - 1) < 0.06), (sl, obs, p)
+
+
+# ------------------------------------------------------- concatenation (A16)
+def test_concatenation_recovers_exact_dos(golden):
+    """Exact ln g cut into overlapping pieces with random offsets is rejoined exactly."""
+    lg = golden.lng("ising_L16_lng.txt")
+    rng = np.random.default_rng(4)
+    for h in (2, 5, 8):
+        c = O.make_config("ising", L=16, n_windows=h)
+        lo, hi = O.layout(c)
+        mask = O.mask_rule(c)
+        WB = hi[0] - lo[0] + 1
+        pieces = np.zeros((h, WB))
+        for a in range(h):
+            pieces[a] = np.where(mask[lo[a]:hi[a] + 1] > 0, lg[lo[a]:hi[a] + 1], 0.0) + \
+                        rng.uniform(-50, 50)
+        out, join = O.concat(c, mask, pieces)
+        ok = mask > 0
+        assert np.max(np.abs(out[ok] - lg[ok])) < 1e-9
+        assert np.all(np.isneginf(out[~ok]))
+        assert np.all(np.diff(join) > 0)
+        for a in range(h - 1):
+            assert lo[a + 1] <= join[a] <= hi[a]
+
+
+# ------------------------------------------------------------ REWL accuracy
+def _concat_error(sim, exact):
+    c = sim.cfg
+    mask = O.mask_rule(c) if c.L >= 4 else (np.isfinite(exact)).astype(np.uint8)
+    out, _ = O.concat(c, mask, sim.pieces())
+    ok = mask > 0
+    return np.abs(out[ok] - exact[ok])
+
+
+def test_rewl_converges_to_exact_ising_L8(golden):
+    """Config-1 geometry (4 windows, o = 3/4) with m = 16 walkers, ln f -> 2^-20."""
+    exact = X.ln_g(golden.counts("ising_q2_L8_counts.txt"))
+    c = O.make_config("ising", L=8, n_windows=4, m=16, kfinal=20, seed=1)
+    sim = O.Sim(c)
+    assert sim.run(100000)
+    err = _concat_error(sim, exact)
+    assert err.max() < 0.08
+
+
+def test_rewl_converges_to_exact_potts_q3_L4(golden):
+    exact = X.ln_g(golden.counts("potts_q3_L4_counts.txt"))
+    c = O.make_config("potts", q=3, L=4, n_windows=3, m=8, kfinal=18, X=5000, seed=2)
+    sim = O.Sim(c)
+    assert sim.run(100000)
+    err = _concat_error(sim, exact)
+    assert err.max() < 0.12
+
+
+def test_rewl_brute_force_potts_q3_L3(golden):
+    """L=3 with the mask taken from enumeration (the closed-form rule needs L >= 4)."""
+    g = golden.counts("potts_q3_L3_counts.txt")
+    exact = X.ln_g(g)
+    mask = (np.array(g) > 0).astype(np.uint8)
+    c = O.make_config("potts", q=3, L=3, n_windows=2, m=8, kfinal=18, X=5000, seed=3)
+    sim = O.Sim(c, mask=mask)
+    assert sim.run(100000)
+    out, _ = O.concat(c, mask, sim.pieces())
+    ok = mask > 0
+    assert np.abs(out[ok] - exact[ok]).max() < 0.12
