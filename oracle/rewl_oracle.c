@@ -176,7 +176,7 @@ struct orc_sim {
     int N, W, h, m, S, WB, log2m;
     int32_t *lo, *hi, *nreach;
     uint8_t* mask;
-    int8_t* spins;    /* S*N: Ising +-1, Potts 0..q-1 */
+    int16_t* spins;   /* S*N: Ising +-1, Potts 0..q-1 */
     int64_t* E;       /* S    */
     int64_t* H;       /* S*WB */
     double* lng;      /* S*WB */
@@ -198,7 +198,7 @@ static int ilog2_exact(int v)
 }
 
 /* Energy change of the proposed move at `site`; for Potts also the new value. */
-static int64_t delta_energy(const orc_sim* s, const int8_t* sp, int site, const uint32_t x[4],
+static int64_t delta_energy(const orc_sim* s, const int16_t* sp, int site, const uint32_t x[4],
                             int* newval)
 {
     int L = s->c.L, xx = site % L, yy = site / L;
@@ -234,7 +234,7 @@ static int64_t dist_to(int64_t b, int64_t lo, int64_t hi)
 static int64_t init_slot(orc_sim* s, int slot)
 {
     int N = s->N, L = s->c.L, a = slot / s->m;
-    int8_t* sp = s->spins + (size_t)slot * N;
+    int16_t* sp = s->spins + (size_t)slot * N;
     int upper = (int64_t)s->lo[a] + s->hi[a] > (int64_t)(s->W - 1);
     for (int y = 0; y < L; ++y)
         for (int x = 0; x < L; ++x) {
@@ -257,7 +257,7 @@ static int64_t init_slot(orc_sim* s, int slot)
         int64_t dE = delta_energy(s, sp, site, x, &nv);
         int64_t nb = bin_of(&s->c, E + dE);
         if (dist_to(nb, lo, hi) <= dist_to(b, lo, hi)) {
-            sp[site] = (int8_t)nv;
+            sp[site] = (int16_t)nv;
             E += dE;
             b = nb;
         }
@@ -312,7 +312,7 @@ orc_sim* orc_create(const orc_config* c, const uint8_t* mask, const double* init
     }
     s->key[0] = (uint32_t)c->seed;
     s->key[1] = (uint32_t)(c->seed >> 32);
-    s->spins = calloc((size_t)s->S * s->N, 1);
+    s->spins = calloc((size_t)s->S * s->N, sizeof(int16_t));
     s->E = calloc(s->S, sizeof(int64_t));
     s->H = calloc((size_t)s->S * s->WB, sizeof(int64_t));
     s->lng = calloc((size_t)s->S * s->WB, sizeof(double));
@@ -360,7 +360,7 @@ static void sweep_slot(orc_sim* s, int slot)
 {
     int a = slot / s->m, N = s->N;
     int64_t X = s->c.exchange_interval, lo = s->lo[a], hi = s->hi[a];
-    int8_t* sp = s->spins + (size_t)slot * N;
+    int16_t* sp = s->spins + (size_t)slot * N;
     int64_t* H = s->H + (size_t)slot * s->WB;
     double* lng = s->lng + (size_t)slot * s->WB;
     int update = !s->done[a];
@@ -376,7 +376,7 @@ static void sweep_slot(orc_sim* s, int slot)
             double delta = lng[b - lo] - lng[nb - lo];
             uint64_t u53 = (((uint64_t)x[3] << 32) | x[2]) >> 11;
             if (orc_accept(delta, u53)) {
-                sp[site] = (int8_t)nv;
+                sp[site] = (int16_t)nv;
                 E += dE;
                 b = nb;
             }
@@ -447,7 +447,7 @@ static void exchange(orc_sim* s)
     int m = s->m, h = s->h, N = s->N, WB = s->WB;
     memset(s->swaps, -1, s->S);
     if (!s->c.exchange_enabled) return;
-    int8_t* tmp = malloc(N);
+    int16_t* tmp = malloc(N * sizeof(int16_t));
     for (int a = (int)(s->t & 1); a + 1 < h; a += 2) {
         uint32_t xc[4];
         draw(s->key, (uint64_t)s->t, (uint32_t)a, TAG_PARTNER, xc);
@@ -468,9 +468,9 @@ static void exchange(orc_sim* s)
                 ok = orc_accept(delta, u53);
             }
             if (ok) {
-                memcpy(tmp, s->spins + (size_t)i * N, N);
-                memcpy(s->spins + (size_t)i * N, s->spins + (size_t)j * N, N);
-                memcpy(s->spins + (size_t)j * N, tmp, N);
+                memcpy(tmp, s->spins + (size_t)i * N, N * sizeof(int16_t));
+                memcpy(s->spins + (size_t)i * N, s->spins + (size_t)j * N, N * sizeof(int16_t));
+                memcpy(s->spins + (size_t)j * N, tmp, N * sizeof(int16_t));
                 int64_t e = s->E[i];
                 s->E[i] = s->E[j];
                 s->E[j] = e;

@@ -201,11 +201,13 @@ def _slots_energy_consistent(sim):
         assert b == st["bins"][sl]
         a = sl // c.walkers_per_window
         assert sim.lo[a] <= b <= sim.hi[a]
+    q = 2 if c.model == 0 else c.q
+    assert st["spins"].max() < q                      # every spin value is a valid state
     return st
 
 
 @pytest.mark.parametrize("model,q,L,h,m", [("ising", 2, 8, 4, 2), ("potts", 3, 4, 3, 4),
-                                           ("potts", 10, 6, 5, 2)])
+                                           ("potts", 10, 6, 5, 2), ("potts", 200, 6, 3, 2)])
 def test_running_energy_equals_recomputed(model, q, L, h, m):
     c = O.make_config(model, q=q, L=L, n_windows=h, m=m, X=500, kfinal=12, seed=9)
     sim = O.Sim(c)
