@@ -1,0 +1,165 @@
+/*
+ * rewl.h -- C ABI of the MI355X replica-exchange Wang-Landau library (librewl.so).
+ *
+ * Method: T. Vogel, Y. W. Li, T. Wuest, D. P. Landau, "Scalable replica-exchange
+ * framework for Wang-Landau sampling", arXiv:1407.5140.  Section references below
+ * are to that paper.
+ *
+ * Conventions
+ *  - Every call returns a rewl_status; no exception crosses the ABI.  On failure
+ *    rewl_last_error() returns a thread-local description.
+ *  - The library owns all device memory it allocates.  Host pointers are owned by
+ *    the caller and only read or written during the call.
+ *  - All device work is ordered on the HIP stream given at creation (NULL = the
+ *    default stream).  Calls that return host data synchronise that stream.
+ *  - A handle holds a batch of one or more independent REWL instances that
+ *    advance together, one exchange interval per step.  Instance indices are
+ *    0-based positions in the configuration array given at creation.
+ *  - Energy bins: Ising E = -sum s_i s_j, bin (E + 2N)/4 in [0, N];
+ *    Potts E = -sum delta(q_i, q_j) (Eq. (2)), bin E + 2N in [0, 2N].
+ *  - A handle must not be used from two threads at once.
+ */
+#ifndef REWL_H
+#define REWL_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    REWL_OK = 0,
+    REWL_E_INVALID = -1,      /* bad argument or configuration                     */
+    REWL_E_EMPTY_WINDOW = -2, /* a window holds no energy level that occurs         */
+    REWL_E_NOMEM = -3,        /* device or host allocation failed                  */
+    REWL_E_DEVICE = -4,       /* a HIP call failed                                  */
+    REWL_E_OVERFLOW = -5,     /* a histogram or the exact-FP64 budget would overflow */
+    REWL_E_INIT_STUCK = -6,   /* a walker could not be driven into its window       */
+    REWL_E_STATE = -7         /* call not valid in the handle's current state       */
+} rewl_status;
+
+/* The problem statement of Sec. II.A and IV (model, lattice, windows h with
+ * overlap o, m walkers per window, flatness, ln f schedule, exchange interval). */
+typedef struct {
+    int32_t model;              /* 0 = 2D Ising (J = 1), 1 = q-state Potts, Eq. (2)      */
+    int32_t q;                  /* Potts states, 3..255 (ignored for Ising)             */
+    int32_t L;                  /* periodic L x L; Ising: even, 4..128; Potts: 4..255    */
+    int32_t n_windows;          /* h >= 1                                               */
+    int32_t overlap_num;        /* overlap o = num/den with the next lower window, 0<=o<1 */
+    int32_t overlap_den;
+    int32_t walkers_per_window; /* m: a power of two, 1..1024                            */
+    int32_t flat_num;           /* flat iff min H >= num/den * mean H (Sec. II.A)        */
+    int32_t flat_den;
+    int32_t lnf_k0;             /* initial ln f = 2^-k0 (Sec. II.A uses ln f = 1: k0=0)  */
+    int32_t lnf_kfinal;         /* window converged once k >= kfinal (ln f <= 2^-kfinal) */
+    int32_t exchange_enabled;   /* 1: replica exchange (Eq. (1)); 0: independent windows */
+    int64_t exchange_interval;  /* flip attempts per walker between exchange steps       */
+    uint64_t seed;              /* Philox4x32-10 key                                     */
+} rewl_config;
+
+/* Optional tuning of a batch (NULL = library choice). */
+typedef struct {
+    int32_t walkers_per_block;  /* walkers staged per LDS tile (power of two <= 64), 0 = auto */
+    int32_t use_graph;          /* 1: replay the interval as a captured HIP graph        */
+    int32_t poll_every;         /* intervals between host checks of the done flags      */
+    int32_t reserved;
+} rewl_tune;
+
+typedef struct rewl_handle rewl_handle;
+
+/* Pure host: global bin count W, bins per window WB, and the window bounds
+ * lo[h], hi[h] (inclusive global bins) of Sec. II.A's partition: equal widths,
+ * overlap >= o up to one bin, first window starts at bin 0, last ends at W-1.
+ * lo/hi may be NULL.  Returns REWL_E_INVALID for a bad configuration.            */
+rewl_status rewl_layout(const rewl_config* cfg, int32_t* n_bins, int32_t* window_bins,
+                        int32_t* lo, int32_t* hi);
+
+/* Pure host: mask[W] = 1 where the energy level occurs on the periodic lattice. */
+rewl_status rewl_mask(const rewl_config* cfg, uint8_t* mask);
+
+/* Create a batch of n >= 1 instances on `hip_stream` (a hipStream_t or NULL).
+ * Validates every configuration before allocating; allocates device state,
+ * and drives every walker into its window (start configurations are ground
+ * states).  *out receives the handle.                                          */
+rewl_status rewl_batch_create(const rewl_config* cfgs, int32_t n, void* hip_stream,
+                              const rewl_tune* tune, rewl_handle** out);
+/* Single-instance form of rewl_batch_create. */
+rewl_status rewl_create(const rewl_config* cfg, void* hip_stream, rewl_handle** out);
+
+/* Warm start: replace every window's ln g by lng[W] (host array, global bins)
+ * before the first interval.  Values must be finite multiples of 2^-20 with
+ * |value| < 2^30 (keeps every later FP64 step exact).  REWL_E_STATE after run. */
+rewl_status rewl_set_initial_lng(rewl_handle* h, int32_t instance, const double* lng);
+
+/* Advance every unfinished instance by up to max_intervals exchange intervals
+ * (Sec. II.A: X attempts per walker, flatness/merge, exchange).  Stops early
+ * once every instance has converged.  *all_done (may be NULL) = 1 when every
+ * window of every instance has reached lnf_kfinal.  Resumable.                */
+rewl_status rewl_run(rewl_handle* h, int64_t max_intervals, int32_t* all_done);
+
+/* Run exactly n intervals with no host polling in between (timing helper). */
+rewl_status rewl_run_exact(rewl_handle* h, int64_t n);
+
+/* ln g of one window over its WB bins (index = global bin - lo): the table the
+ * window's walkers share since its last merge (Sec. II.A "merge and average");
+ * for a converged window this is its result, before the first merge it is the
+ * starting table (zero or the warm start).                                      */
+rewl_status rewl_get_window_lng(rewl_handle* h, int32_t instance, int32_t window, double* out);
+
+/* Sec. II.B concatenation of the h pieces into ln g over all W bins (-inf where
+ * a level does not occur), normalised to sum_E g(E) = q^N (Ising: 2^N).  join
+ * (h-1 entries, may be NULL) receives the join bins.  Runs on the device.      */
+rewl_status rewl_concat(rewl_handle* h, int32_t instance, double* out_lng, int32_t* join);
+
+/* Full state of one instance for inspection (S = h*m slots, slot = a*m + r):
+ *   spins[S*N] (Ising 1 = up; Potts 0..q-1), bins[S], H[S*WB], lng[S*WB]
+ *   (each walker's ln g), flat[S], k[h], done[h], swaps[S] (1 exchanged in the
+ *   last interval, 0 proposed and rejected, -1 not proposed), *t = completed
+ *   intervals.  Any pointer may be NULL.                                        */
+rewl_status rewl_get_state(rewl_handle* h, int32_t instance, uint8_t* spins, int32_t* bins,
+                           int64_t* H, double* lng, uint8_t* flat, int32_t* k, uint8_t* done,
+                           int8_t* swaps, int64_t* t);
+
+typedef struct {
+    int64_t intervals;          /* completed intervals                                 */
+    int64_t attempts;           /* flip attempts made (all walkers)                    */
+    int32_t windows_done;
+    int32_t min_k;              /* smallest ln f exponent over windows                 */
+    double sweep_ms;            /* summed device time of the sweep launches (events)   */
+    double interval_ms;         /* summed device time of whole intervals (events)      */
+} rewl_stats;
+
+/* Counters of one instance; ex_prop/ex_acc (h entries each, may be NULL):
+ * proposed and accepted exchanges per window pair (a, a+1).                     */
+rewl_status rewl_get_stats(rewl_handle* h, int32_t instance, rewl_stats* out, int64_t* ex_prop,
+                           int64_t* ex_acc);
+
+/* Enable (1) or disable (0) per-launch event timing of the sweep kernel. */
+rewl_status rewl_set_timing(rewl_handle* h, int32_t on);
+
+/* Checkpoint: *len receives the byte size; with buf != NULL the state of all
+ * instances is written to buf (len bytes).  Restore requires a handle created
+ * from the same configurations.  Philox is counter-based, so a restored run
+ * continues bit for bit.                                                        */
+rewl_status rewl_checkpoint(rewl_handle* h, void* buf, size_t* len);
+rewl_status rewl_restore(rewl_handle* h, const void* buf, size_t len);
+
+void rewl_destroy(rewl_handle* h);
+const char* rewl_last_error(void);
+
+/* Number of instances and the chosen walkers-per-block of one instance. */
+rewl_status rewl_info(rewl_handle* h, int32_t instance, int32_t* n_instances,
+                      int32_t* walkers_per_block, size_t* lds_bytes);
+
+/* Diagnostics (run on the device, used by the tests):
+ * the full acceptance predicate u53 < 2^53 exp(delta) for n pairs: out[i] =
+ * 1/0 decided by the fast test, 3/2 accepted/rejected by the exact slow path;
+ * Philox4x32-10 blocks: in[6 n] = (ctr0..3, key0, key1), out[4 n].               */
+rewl_status rewl_probe_accept(const double* delta, const uint64_t* u53, int32_t n, int32_t* out);
+rewl_status rewl_probe_philox(const uint32_t* in, int32_t n, uint32_t* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,276 @@
+"""Replica-exchange Wang-Landau (arXiv:1407.5140) on MI355X: Python binding.
+
+This module only marshals arguments to librewl.so (include/rewl.h); every step
+of the method runs in the library's HIP kernels.  The library must have been
+built in-tree (``python -m paper_1407_5140_amd.build``); importing without it
+raises, there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "librewl.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1407_5140_amd.build` "
+                      "(hipcc, gfx950); the REWL path has no CPU fallback")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+REWL_OK = 0
+_STATUS = {0: "OK", -1: "INVALID", -2: "EMPTY_WINDOW", -3: "NOMEM", -4: "DEVICE", -5: "OVERFLOW",
+           -6: "INIT_STUCK", -7: "STATE"}
+
+
+class RewlError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        msg = _lib.rewl_last_error().decode(errors="replace")
+        super().__init__(f"{where}: REWL_E_{_STATUS.get(status, status)} ({status}): {msg}")
+        self.status = status
+
+
+class rewl_config(ctypes.Structure):
+    _fields_ = [("model", ctypes.c_int32), ("q", ctypes.c_int32), ("L", ctypes.c_int32),
+                ("n_windows", ctypes.c_int32), ("overlap_num", ctypes.c_int32),
+                ("overlap_den", ctypes.c_int32), ("walkers_per_window", ctypes.c_int32),
+                ("flat_num", ctypes.c_int32), ("flat_den", ctypes.c_int32),
+                ("lnf_k0", ctypes.c_int32), ("lnf_kfinal", ctypes.c_int32),
+                ("exchange_enabled", ctypes.c_int32), ("exchange_interval", ctypes.c_int64),
+                ("seed", ctypes.c_uint64)]
+
+
+class rewl_tune(ctypes.Structure):
+    _fields_ = [("walkers_per_block", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("poll_every", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class rewl_stats(ctypes.Structure):
+    _fields_ = [("intervals", ctypes.c_int64), ("attempts", ctypes.c_int64),
+                ("windows_done", ctypes.c_int32), ("min_k", ctypes.c_int32),
+                ("sweep_ms", ctypes.c_double), ("interval_ms", ctypes.c_double)]
+
+
+_vp = ctypes.c_void_p
+_P = ctypes.POINTER
+_sigs = {
+    "rewl_last_error": ([], ctypes.c_char_p),
+    "rewl_layout": ([_P(rewl_config), _vp, _vp, _vp, _vp], ctypes.c_int),
+    "rewl_mask": ([_P(rewl_config), _vp], ctypes.c_int),
+    "rewl_create": ([_P(rewl_config), _vp, _P(_vp)], ctypes.c_int),
+    "rewl_batch_create": ([_P(rewl_config), ctypes.c_int32, _vp, _P(rewl_tune), _P(_vp)], ctypes.c_int),
+    "rewl_set_initial_lng": ([_vp, ctypes.c_int32, _vp], ctypes.c_int),
+    "rewl_run": ([_vp, ctypes.c_int64, _P(ctypes.c_int32)], ctypes.c_int),
+    "rewl_run_exact": ([_vp, ctypes.c_int64], ctypes.c_int),
+    "rewl_get_window_lng": ([_vp, ctypes.c_int32, ctypes.c_int32, _vp], ctypes.c_int),
+    "rewl_concat": ([_vp, ctypes.c_int32, _vp, _vp], ctypes.c_int),
+    "rewl_get_state": ([_vp, ctypes.c_int32] + [_vp] * 9, ctypes.c_int),
+    "rewl_get_stats": ([_vp, ctypes.c_int32, _P(rewl_stats), _vp, _vp], ctypes.c_int),
+    "rewl_set_timing": ([_vp, ctypes.c_int32], ctypes.c_int),
+    "rewl_checkpoint": ([_vp, _vp, _P(ctypes.c_size_t)], ctypes.c_int),
+    "rewl_restore": ([_vp, _vp, ctypes.c_size_t], ctypes.c_int),
+    "rewl_destroy": ([_vp], None),
+    "rewl_info": ([_vp, ctypes.c_int32, _vp, _vp, _vp], ctypes.c_int),
+    "rewl_probe_accept": ([_vp, _vp, ctypes.c_int32, _vp], ctypes.c_int),
+    "rewl_probe_philox": ([_vp, ctypes.c_int32, _vp], ctypes.c_int),
+}
+for _name, (_args, _res) in _sigs.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _res
+
+EXPORTED = tuple(_sigs)
+
+
+def _check(status: int, where: str) -> None:
+    if status != REWL_OK:
+        raise RewlError(status, where)
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(_vp)
+
+
+def make_config(model="ising", q=2, L=8, n_windows=4, overlap=(3, 4), m=1, flat=(4, 5), k0=0,
+                kfinal=20, X=10000, seed=1, exchange=True) -> rewl_config:
+    """Problem statement of Sec. II.A / IV: model, L, h windows with overlap o,
+    m walkers per window, flatness num/den, ln f = 2^-k0 .. 2^-kfinal, X attempts
+    per walker between exchanges, Philox seed."""
+    return rewl_config(0 if model == "ising" else 1, q, L, n_windows, overlap[0], overlap[1], m,
+                       flat[0], flat[1], k0, kfinal, 1 if exchange else 0, X, seed)
+
+
+# ------------------------------------------------------------ C-ABI mirrors
+def rewl_layout(cfg: rewl_config):
+    nb, wb = ctypes.c_int32(), ctypes.c_int32()
+    lo = np.zeros(cfg.n_windows, np.int32)
+    hi = np.zeros(cfg.n_windows, np.int32)
+    _check(_lib.rewl_layout(ctypes.byref(cfg), ctypes.byref(nb), ctypes.byref(wb), _p(lo), _p(hi)),
+           "rewl_layout")
+    return nb.value, wb.value, lo, hi
+
+
+def rewl_mask(cfg: rewl_config) -> np.ndarray:
+    W = rewl_layout(cfg)[0]
+    m = np.zeros(W, np.uint8)
+    _check(_lib.rewl_mask(ctypes.byref(cfg), _p(m)), "rewl_mask")
+    return m
+
+
+def rewl_create(cfg: rewl_config, stream=None):
+    h = _vp()
+    _check(_lib.rewl_create(ctypes.byref(cfg), stream, ctypes.byref(h)), "rewl_create")
+    return h
+
+
+def rewl_batch_create(cfgs, stream=None, tune: rewl_tune | None = None):
+    arr = (rewl_config * len(cfgs))(*cfgs)
+    h = _vp()
+    _check(_lib.rewl_batch_create(arr, len(cfgs), stream, ctypes.byref(tune) if tune else None,
+                                  ctypes.byref(h)), "rewl_batch_create")
+    return h
+
+
+def rewl_set_initial_lng(h, instance: int, lng: np.ndarray) -> None:
+    a = np.ascontiguousarray(lng, dtype=np.float64)
+    _check(_lib.rewl_set_initial_lng(h, instance, _p(a)), "rewl_set_initial_lng")
+
+
+def rewl_run(h, max_intervals: int) -> bool:
+    done = ctypes.c_int32(0)
+    _check(_lib.rewl_run(h, int(max_intervals), ctypes.byref(done)), "rewl_run")
+    return bool(done.value)
+
+
+def rewl_run_exact(h, n: int) -> None:
+    _check(_lib.rewl_run_exact(h, int(n)), "rewl_run_exact")
+
+
+def rewl_get_window_lng(h, instance: int, window: int, WB: int) -> np.ndarray:
+    out = np.empty(WB, np.float64)
+    _check(_lib.rewl_get_window_lng(h, instance, window, _p(out)), "rewl_get_window_lng")
+    return out
+
+
+def rewl_concat(h, instance: int, W: int, n_windows: int):
+    out = np.empty(W, np.float64)
+    join = np.zeros(max(n_windows - 1, 1), np.int32)
+    _check(_lib.rewl_concat(h, instance, _p(out), _p(join)), "rewl_concat")
+    return out, join[: max(n_windows - 1, 0)]
+
+
+def rewl_get_state(h, instance: int, cfg: rewl_config) -> dict:
+    W, WB, _, _ = rewl_layout(cfg)
+    S, N, nw = cfg.n_windows * cfg.walkers_per_window, cfg.L * cfg.L, cfg.n_windows
+    st = dict(spins=np.empty((S, N), np.uint8), bins=np.empty(S, np.int32),
+              H=np.empty((S, WB), np.int64), lng=np.empty((S, WB), np.float64),
+              flat=np.empty(S, np.uint8), k=np.empty(nw, np.int32), done=np.empty(nw, np.uint8),
+              swaps=np.empty(S, np.int8))
+    t = ctypes.c_int64(0)
+    _check(_lib.rewl_get_state(h, instance, *[_p(st[n]) for n in
+                                              ("spins", "bins", "H", "lng", "flat", "k", "done",
+                                               "swaps")], ctypes.byref(t)), "rewl_get_state")
+    st["t"] = t.value
+    return st
+
+
+def rewl_get_stats(h, instance: int, n_windows: int) -> dict:
+    s = rewl_stats()
+    p = np.zeros(n_windows, np.int64)
+    a = np.zeros(n_windows, np.int64)
+    _check(_lib.rewl_get_stats(h, instance, ctypes.byref(s), _p(p), _p(a)), "rewl_get_stats")
+    return dict(intervals=s.intervals, attempts=s.attempts, windows_done=s.windows_done,
+                min_k=s.min_k, sweep_ms=s.sweep_ms, interval_ms=s.interval_ms, ex_prop=p, ex_acc=a)
+
+
+def rewl_set_timing(h, on: bool) -> None:
+    _check(_lib.rewl_set_timing(h, 1 if on else 0), "rewl_set_timing")
+
+
+def rewl_checkpoint(h) -> bytes:
+    n = ctypes.c_size_t(0)
+    _check(_lib.rewl_checkpoint(h, None, ctypes.byref(n)), "rewl_checkpoint")
+    buf = ctypes.create_string_buffer(n.value)
+    _check(_lib.rewl_checkpoint(h, buf, ctypes.byref(n)), "rewl_checkpoint")
+    return buf.raw[: n.value]
+
+
+def rewl_restore(h, blob: bytes) -> None:
+    buf = ctypes.create_string_buffer(blob, len(blob))
+    _check(_lib.rewl_restore(h, buf, len(blob)), "rewl_restore")
+
+
+def rewl_destroy(h) -> None:
+    _lib.rewl_destroy(h)
+
+
+def rewl_info(h, instance: int = 0) -> dict:
+    n, w, lds = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_size_t()
+    _check(_lib.rewl_info(h, instance, ctypes.byref(n), ctypes.byref(w), ctypes.byref(lds)),
+           "rewl_info")
+    return dict(n_instances=n.value, walkers_per_block=w.value, lds_bytes=lds.value)
+
+
+def rewl_probe_accept(delta, u53) -> np.ndarray:
+    d = np.ascontiguousarray(delta, dtype=np.float64)
+    u = np.ascontiguousarray(u53, dtype=np.uint64)
+    out = np.empty(len(d), np.int32)
+    _check(_lib.rewl_probe_accept(_p(d), _p(u), len(d), _p(out)), "rewl_probe_accept")
+    return out
+
+
+def rewl_probe_philox(ctr_key: np.ndarray) -> np.ndarray:
+    a = np.ascontiguousarray(ctr_key, dtype=np.uint32).reshape(-1, 6)
+    out = np.empty((len(a), 4), np.uint32)
+    _check(_lib.rewl_probe_philox(_p(a), len(a), _p(out)), "rewl_probe_philox")
+    return out
+
+
+# ------------------------------------------------------------ convenience
+class Rewl:
+    """One handle (a batch of instances) with the C-ABI calls as methods."""
+
+    def __init__(self, cfgs, stream=None, tune: rewl_tune | None = None):
+        self.cfgs = list(cfgs) if isinstance(cfgs, (list, tuple)) else [cfgs]
+        self.h = rewl_batch_create(self.cfgs, stream, tune)
+        self.layouts = [rewl_layout(c) for c in self.cfgs]
+
+    def close(self):
+        if self.h:
+            rewl_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def run(self, max_intervals: int) -> bool:
+        return rewl_run(self.h, max_intervals)
+
+    def run_exact(self, n: int) -> None:
+        rewl_run_exact(self.h, n)
+
+    def state(self, i: int = 0) -> dict:
+        return rewl_get_state(self.h, i, self.cfgs[i])
+
+    def stats(self, i: int = 0) -> dict:
+        return rewl_get_stats(self.h, i, self.cfgs[i].n_windows)
+
+    def pieces(self, i: int = 0) -> np.ndarray:
+        W, WB, lo, hi = self.layouts[i]
+        return np.stack([rewl_get_window_lng(self.h, i, a, WB) for a in range(len(lo))])
+
+    def concat(self, i: int = 0):
+        W = self.layouts[i][0]
+        return rewl_concat(self.h, i, W, self.cfgs[i].n_windows)
+
+    def set_initial_lng(self, lng, i: int = 0) -> None:
+        rewl_set_initial_lng(self.h, i, lng)
+
+    def info(self, i: int = 0) -> dict:
+        return rewl_info(self.h, i)

@@ -1,0 +1,788 @@
+// rewl_api.hip -- host side of librewl: validation, layout, device state,
+// the interval launch sequence (plain or as a replayed HIP graph) and the C ABI.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/rewl.h"
+#include "rewl_kernels.hip"
+
+using namespace rewl;
+
+namespace {
+
+thread_local std::string g_err;
+
+rewl_status fail(rewl_status s, const std::string& msg)
+{
+    g_err = msg;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return fail(REWL_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));     \
+    } while (0)
+
+int ilog2_exact(int64_t v)
+{
+    int j = 0;
+    while ((int64_t(1) << j) < v) ++j;
+    return (int64_t(1) << j) == v ? j : -1;
+}
+
+int64_t n_bins_of(const rewl_config& c)
+{
+    const int64_t N = (int64_t)c.L * c.L;
+    return c.model == 0 ? N + 1 : 2 * N + 1;
+}
+
+// Sec. II.A partition: h windows of equal width w over S = W-1 bin steps, each
+// sharing at least a fraction o of its width with the next lower window (up to
+// one bin lost to integer starts); width w = ceil(S den / (den + (h-1)(den-num))),
+// start a = floor(a (S - w) / (h - 1)).  This reproduces the Potts example of
+// Sec. IV.A: width 1000, shift 250, 77/317/717/1277 windows for L = 100..400.
+bool layout_of(const rewl_config& c, std::vector<int32_t>& lo, std::vector<int32_t>& hi)
+{
+    const int64_t S = n_bins_of(c) - 1, h = c.n_windows, num = c.overlap_num, den = c.overlap_den;
+    if (h < 1 || den < 1 || num < 0 || num >= den) return false;
+    lo.assign(h, 0);
+    hi.assign(h, 0);
+    if (h == 1) {
+        hi[0] = (int32_t)S;
+        return true;
+    }
+    const int64_t D = den + (h - 1) * (den - num);
+    int64_t w = (S * den + D - 1) / D;
+    if (w > S) w = S;
+    for (int64_t a = 0; a < h; ++a) {
+        lo[a] = (int32_t)(a * (S - w) / (h - 1));
+        hi[a] = (int32_t)(lo[a] + w);
+    }
+    return true;
+}
+
+// Levels that never occur on the periodic lattice: Ising (even L) E = -2N+4 and
+// 2N-4; Potts (q >= 3, L >= 4) one, two, three or five broken bonds.
+void mask_of(const rewl_config& c, std::vector<uint8_t>& mask)
+{
+    const int64_t W = n_bins_of(c), N = (int64_t)c.L * c.L;
+    mask.assign(W, 1);
+    if (c.model == 0) {
+        mask[1] = 0;
+        mask[N - 1] = 0;
+    } else {
+        mask[1] = mask[2] = mask[3] = mask[5] = 0;
+    }
+}
+
+rewl_status validate(const rewl_config& c)
+{
+    if (c.model != 0 && c.model != 1) return fail(REWL_E_INVALID, "model must be 0 (Ising) or 1 (Potts)");
+    if (c.model == 0 && (c.L < 4 || c.L > 128 || c.L % 2))
+        return fail(REWL_E_INVALID, "Ising needs an even L in [4, 128]");
+    if (c.model == 1 && (c.L < 4 || c.L > 255)) return fail(REWL_E_INVALID, "Potts needs L in [4, 255]");
+    if (c.model == 1 && (c.q < 3 || c.q > 255)) return fail(REWL_E_INVALID, "Potts needs q in [3, 255]");
+    if (c.n_windows < 1) return fail(REWL_E_INVALID, "n_windows must be >= 1");
+    if (c.overlap_den < 1 || c.overlap_num < 0 || c.overlap_num >= c.overlap_den)
+        return fail(REWL_E_INVALID, "overlap must be num/den in [0, 1)");
+    if (c.walkers_per_window < 1 || c.walkers_per_window > 1024 || ilog2_exact(c.walkers_per_window) < 0)
+        return fail(REWL_E_INVALID, "walkers_per_window must be a power of two in [1, 1024]");
+    if (c.flat_den < 1 || c.flat_num < 0 || c.flat_num > c.flat_den)
+        return fail(REWL_E_INVALID, "flatness must be num/den in [0, 1]");
+    if (c.lnf_k0 < 0 || c.lnf_kfinal <= c.lnf_k0 || c.lnf_kfinal > 40)
+        return fail(REWL_E_INVALID, "need 0 <= lnf_k0 < lnf_kfinal <= 40");
+    if (c.exchange_interval < 1 || c.exchange_interval > (int64_t(1) << 31))
+        return fail(REWL_E_INVALID, "exchange_interval must be in [1, 2^31]");
+    if (c.exchange_enabled != 0 && c.exchange_enabled != 1)
+        return fail(REWL_E_INVALID, "exchange_enabled must be 0 or 1");
+    std::vector<int32_t> lo, hi;
+    if (!layout_of(c, lo, hi)) return fail(REWL_E_INVALID, "bad layout");
+    if (hi[0] - lo[0] < 1) return fail(REWL_E_INVALID, "windows narrower than two bins");
+    if ((int64_t)c.n_windows * c.walkers_per_window > (int64_t(1) << 24))
+        return fail(REWL_E_INVALID, "too many walkers");
+    std::vector<uint8_t> mask;
+    mask_of(c, mask);
+    for (int a = 0; a < c.n_windows; ++a) {
+        int n = 0;
+        for (int b = lo[a]; b <= hi[a]; ++b) n += mask[b];
+        if (n < 1) return fail(REWL_E_EMPTY_WINDOW, "window " + std::to_string(a) + " is empty");
+    }
+    return REWL_OK;
+}
+
+struct HostInst {
+    rewl_config cfg;
+    int N, W, h, m, S, WB, log2m, wpr, wpb;
+    size_t lds;
+    std::vector<int32_t> lo, hi, nreach;
+    std::vector<uint8_t> mask;
+    Inst dev;
+};
+
+}  // namespace
+
+struct rewl_handle {
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int n = 0;
+    std::vector<HostInst> inst;
+    std::vector<void*> allocs;
+    Inst* d_insts = nullptr;
+    Tile* d_tiles = nullptr;
+    int ntiles = 0;
+    int2* d_merge = nullptr;
+    int nmerge = 0;
+    int32_t* d_rng_start = nullptr;
+    int rng_grid = 0;
+    int32_t* d_exch_start = nullptr;
+    int exch_threads = 0;
+    int32_t* d_slot_start = nullptr;
+    int slot_threads = 0;
+    size_t max_lds = 0;
+    InstCtr* d_ctr = nullptr;
+    InstCtr* h_ctr = nullptr;   // pinned
+    bool started = false;
+    rewl_tune tune{};
+    hipGraphExec_t gexec = nullptr;
+    bool timing = false;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    double sweep_ms = 0.0, interval_ms = 0.0;
+
+    template <class T>
+    rewl_status alloc(T** p, size_t count)
+    {
+        void* q = nullptr;
+        if (count == 0) count = 1;
+        hipError_t e = hipMalloc(&q, count * sizeof(T));
+        if (e != hipSuccess) return fail(REWL_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+        allocs.push_back(q);
+        *p = (T*)q;
+        return REWL_OK;
+    }
+};
+
+namespace {
+
+rewl_status enqueue_interval(rewl_handle* H, bool time_it)
+{
+    if (time_it) HIP_TRY(hipEventRecord(H->ev[0], H->stream));
+    hipLaunchKernelGGL(k_rng, dim3(H->rng_grid), dim3(256), 0, H->stream, H->d_insts,
+                       H->d_rng_start, H->n);
+    if (time_it) HIP_TRY(hipEventRecord(H->ev[1], H->stream));
+    hipLaunchKernelGGL(k_sweep, dim3(H->ntiles), dim3(64), H->max_lds, H->stream, H->d_insts,
+                       H->d_tiles, H->ntiles);
+    if (time_it) HIP_TRY(hipEventRecord(H->ev[2], H->stream));
+    hipLaunchKernelGGL(k_merge, dim3(H->nmerge), dim3(256), 0, H->stream, H->d_insts, H->d_merge);
+    if (H->exch_threads > 0)
+        hipLaunchKernelGGL(k_exchange, dim3((H->exch_threads + 255) / 256), dim3(256), 0, H->stream,
+                           H->d_insts, H->d_exch_start, H->n);
+    hipLaunchKernelGGL(k_advance, dim3((H->n + 63) / 64), dim3(64), 0, H->stream, H->d_insts, H->n);
+    if (time_it) HIP_TRY(hipEventRecord(H->ev[3], H->stream));
+    HIP_TRY(hipGetLastError());
+    return REWL_OK;
+}
+
+rewl_status step(rewl_handle* H)
+{
+    if (H->tune.use_graph && !H->timing) {
+        if (!H->gexec) {
+            hipGraph_t g;
+            HIP_TRY(hipStreamBeginCapture(H->stream, hipStreamCaptureModeThreadLocal));
+            rewl_status s = enqueue_interval(H, false);
+            hipError_t e = hipStreamEndCapture(H->stream, &g);
+            if (s != REWL_OK) return s;
+            HIP_TRY(e);
+            HIP_TRY(hipGraphInstantiate(&H->gexec, g, nullptr, nullptr, 0));
+            HIP_TRY(hipGraphDestroy(g));
+        }
+        HIP_TRY(hipGraphLaunch(H->gexec, H->stream));
+        return REWL_OK;
+    }
+    rewl_status s = enqueue_interval(H, H->timing);
+    if (s != REWL_OK) return s;
+    if (H->timing) {
+        HIP_TRY(hipEventSynchronize(H->ev[3]));
+        float ms = 0.f, ms2 = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, H->ev[1], H->ev[2]));
+        HIP_TRY(hipEventElapsedTime(&ms2, H->ev[0], H->ev[3]));
+        H->sweep_ms += ms;
+        H->interval_ms += ms2;
+    }
+    return REWL_OK;
+}
+
+rewl_status sync_flags(rewl_handle* H, bool* all_done)
+{
+    HIP_TRY(hipMemcpyAsync(H->h_ctr, H->d_ctr, sizeof(InstCtr) * H->n, hipMemcpyDeviceToHost, H->stream));
+    HIP_TRY(hipStreamSynchronize(H->stream));
+    bool all = true;
+    for (int i = 0; i < H->n; ++i) {
+        const InstCtr& c = H->h_ctr[i];
+        if (c.err & kErrInitStuck) return fail(REWL_E_INIT_STUCK, "instance " + std::to_string(i) + ": walker stuck outside its window");
+        if (c.err & kErrOverflow) return fail(REWL_E_OVERFLOW, "instance " + std::to_string(i) + ": histogram count near 2^32");
+        if (c.err & kErrExactness) return fail(REWL_E_OVERFLOW, "instance " + std::to_string(i) + ": ln g outside the exact FP64 budget");
+        all = all && c.all_done;
+    }
+    if (all_done) *all_done = all;
+    return REWL_OK;
+}
+
+rewl_status check_inst(rewl_handle* H, int32_t i)
+{
+    if (!H) return fail(REWL_E_INVALID, "null handle");
+    if (i < 0 || i >= H->n) return fail(REWL_E_INVALID, "instance index out of range");
+    return REWL_OK;
+}
+
+}  // namespace
+
+// ---- checkpoint: per instance the arrays below, in this order
+namespace {
+struct Span {
+    void* dev;
+    size_t bytes;
+};
+std::vector<Span> spans_of(rewl_handle* H, int i)
+{
+    HostInst& hi = H->inst[i];
+    Inst& d = hi.dev;
+    const size_t S = hi.S, h = hi.h, WB = hi.WB;
+    std::vector<Span> v;
+    if (d.model == 0) v.push_back({d.lat, (size_t)hi.cfg.L * hi.wpr * S * 8});
+    else v.push_back({d.plat, (size_t)hi.N * S});
+    v.push_back({d.bin, S * 4});
+    v.push_back({d.H, h * WB * hi.m * 4});
+    v.push_back({d.base, h * WB * 8});
+    v.push_back({d.k, h * 4});
+    v.push_back({d.done, h * 4});
+    v.push_back({d.flat, S});
+    v.push_back({d.swaps, S});
+    v.push_back({d.ex_prop, h * 8});
+    v.push_back({d.ex_acc, h * 8});
+    v.push_back({d.merges, h * 4});
+    v.push_back({d.ctr, sizeof(InstCtr)});
+    return v;
+}
+}  // namespace
+
+extern "C" {
+
+const char* rewl_last_error(void) { return g_err.c_str(); }
+
+rewl_status rewl_layout(const rewl_config* cfg, int32_t* n_bins, int32_t* window_bins, int32_t* lo,
+                        int32_t* hi)
+{
+    if (!cfg) return fail(REWL_E_INVALID, "null config");
+    rewl_status s = validate(*cfg);
+    if (s != REWL_OK) return s;
+    std::vector<int32_t> l, u;
+    layout_of(*cfg, l, u);
+    if (n_bins) *n_bins = (int32_t)n_bins_of(*cfg);
+    if (window_bins) *window_bins = u[0] - l[0] + 1;
+    if (lo) std::copy(l.begin(), l.end(), lo);
+    if (hi) std::copy(u.begin(), u.end(), hi);
+    return REWL_OK;
+}
+
+rewl_status rewl_mask(const rewl_config* cfg, uint8_t* mask)
+{
+    if (!cfg || !mask) return fail(REWL_E_INVALID, "null argument");
+    rewl_status s = validate(*cfg);
+    if (s != REWL_OK) return s;
+    std::vector<uint8_t> m;
+    mask_of(*cfg, m);
+    std::copy(m.begin(), m.end(), mask);
+    return REWL_OK;
+}
+
+void rewl_destroy(rewl_handle* H)
+{
+    if (!H) return;
+    if (H->stream) (void)hipStreamSynchronize(H->stream);
+    if (H->gexec) (void)hipGraphExecDestroy(H->gexec);
+    for (hipEvent_t e : H->ev)
+        if (e) (void)hipEventDestroy(e);
+    for (void* p : H->allocs) (void)hipFree(p);
+    if (H->h_ctr) (void)hipHostFree(H->h_ctr);
+    if (H->own_stream && H->stream) (void)hipStreamDestroy(H->stream);
+    delete H;
+}
+
+static rewl_status create_impl(const rewl_config* cfgs, int32_t n, void* hip_stream,
+                               const rewl_tune* tune, rewl_handle** out)
+{
+    if (!cfgs || !out || n < 1) return fail(REWL_E_INVALID, "need n >= 1 configurations");
+    *out = nullptr;
+    for (int i = 0; i < n; ++i) {
+        rewl_status s = validate(cfgs[i]);
+        if (s != REWL_OK) return fail(s, "instance " + std::to_string(i) + ": " + g_err);
+    }
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    int lds_limit = 0;
+    HIP_TRY(hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    if (lds_limit <= 0) lds_limit = 65536;
+
+    rewl_handle* H = new rewl_handle();
+    if (tune) H->tune = *tune;
+    if (H->tune.poll_every <= 0) H->tune.poll_every = 8;
+    H->n = n;
+    H->inst.resize(n);
+    std::vector<Inst> devs(n);
+    std::vector<Tile> tiles;
+    std::vector<int2> merges;
+    std::vector<int32_t> rng_start(1, 0), exch_start(1, 0), slot_start(1, 0);
+    auto bail = [&](rewl_status s) {
+        rewl_destroy(H);
+        return s;
+    };
+    if (hip_stream) {
+        H->stream = (hipStream_t)hip_stream;
+    } else {
+        hipError_t e = hipStreamCreate(&H->stream);
+        if (e != hipSuccess) return bail(fail(REWL_E_DEVICE, "hipStreamCreate failed"));
+        H->own_stream = true;
+    }
+    for (int k = 0; k < 4; ++k)
+        if (hipEventCreate(&H->ev[k]) != hipSuccess) return bail(fail(REWL_E_DEVICE, "hipEventCreate failed"));
+
+    for (int i = 0; i < n; ++i) {
+        HostInst& hi = H->inst[i];
+        hi.cfg = cfgs[i];
+        const rewl_config& c = hi.cfg;
+        hi.N = c.L * c.L;
+        hi.W = (int)n_bins_of(c);
+        hi.h = c.n_windows;
+        hi.m = c.walkers_per_window;
+        hi.S = hi.h * hi.m;
+        hi.log2m = ilog2_exact(hi.m);
+        hi.wpr = c.model == 0 ? (c.L + 63) / 64 : 1;
+        layout_of(c, hi.lo, hi.hi);
+        mask_of(c, hi.mask);
+        hi.WB = hi.hi[0] - hi.lo[0] + 1;
+        hi.nreach.assign(hi.h, 0);
+        for (int a = 0; a < hi.h; ++a)
+            for (int b = hi.lo[a]; b <= hi.hi[a]; ++b) hi.nreach[a] += hi.mask[b];
+        int want = H->tune.walkers_per_block > 0 ? H->tune.walkers_per_block : 64;
+        int wpb = 1;
+        while (wpb * 2 <= std::min(want, std::min(64, hi.m))) wpb *= 2;
+        while (wpb > 1 && sweep_lds_bytes(c.model, c.L, hi.wpr, hi.WB, wpb) > (size_t)lds_limit) wpb /= 2;
+        hi.wpb = wpb;
+        hi.lds = sweep_lds_bytes(c.model, c.L, hi.wpr, hi.WB, wpb);
+        if (hi.lds > (size_t)lds_limit)
+            return bail(fail(REWL_E_INVALID, "instance " + std::to_string(i) + ": one walker's tables exceed LDS"));
+        H->max_lds = std::max(H->max_lds, hi.lds);
+
+        Inst& d = hi.dev;
+        std::memset(&d, 0, sizeof(d));
+        d.model = c.model; d.q = c.model ? c.q : 2; d.L = c.L; d.N = hi.N; d.W = hi.W; d.h = hi.h;
+        d.m = hi.m; d.S = hi.S; d.WB = hi.WB; d.log2m = hi.log2m; d.flat_num = c.flat_num;
+        d.flat_den = c.flat_den; d.kfinal = c.lnf_kfinal; d.exch = c.exchange_enabled; d.wpr = hi.wpr;
+        d.X = c.exchange_interval; d.k0 = (uint32_t)c.seed; d.k1 = (uint32_t)(c.seed >> 32);
+        const size_t S = hi.S, h = hi.h, WB = hi.WB;
+        rewl_status s = REWL_OK;
+        if (c.model == 0) s = H->alloc(&d.lat, (size_t)c.L * hi.wpr * S);
+        else s = H->alloc(&d.plat, (size_t)hi.N * S);
+        if (s == REWL_OK) s = H->alloc(&d.bin, S);
+        if (s == REWL_OK) s = H->alloc(&d.H, h * WB * hi.m);
+        if (s == REWL_OK) s = H->alloc(&d.base, h * WB);
+        if (s == REWL_OK) s = H->alloc(&d.lo, h);
+        if (s == REWL_OK) s = H->alloc(&d.hi, h);
+        if (s == REWL_OK) s = H->alloc(&d.nreach, h);
+        if (s == REWL_OK) s = H->alloc(&d.mask, hi.W);
+        if (s == REWL_OK) s = H->alloc(&d.k, h);
+        if (s == REWL_OK) s = H->alloc(&d.done, h);
+        if (s == REWL_OK) s = H->alloc(&d.flat, S);
+        if (s == REWL_OK) s = H->alloc(&d.swaps, S);
+        if (s == REWL_OK) s = H->alloc(&d.rpack, (size_t)c.exchange_interval * S);
+        if (s == REWL_OK) s = H->alloc(&d.rv, (size_t)c.exchange_interval * S);
+        if (s == REWL_OK) s = H->alloc(&d.ex_prop, h);
+        if (s == REWL_OK) s = H->alloc(&d.ex_acc, h);
+        if (s == REWL_OK) s = H->alloc(&d.merges, h);
+        if (s != REWL_OK) return bail(s);
+
+        std::vector<int32_t> kinit(h, c.lnf_k0), zeros(h, 0);
+        std::vector<int32_t> merges0(h, -1);
+        hipStream_t st = H->stream;
+        bool ok = true;
+        ok &= hipMemcpyAsync(d.lo, hi.lo.data(), h * 4, hipMemcpyHostToDevice, st) == hipSuccess;
+        ok &= hipMemcpyAsync(d.hi, hi.hi.data(), h * 4, hipMemcpyHostToDevice, st) == hipSuccess;
+        ok &= hipMemcpyAsync(d.nreach, hi.nreach.data(), h * 4, hipMemcpyHostToDevice, st) == hipSuccess;
+        ok &= hipMemcpyAsync(d.mask, hi.mask.data(), hi.W, hipMemcpyHostToDevice, st) == hipSuccess;
+        ok &= hipMemcpyAsync(d.k, kinit.data(), h * 4, hipMemcpyHostToDevice, st) == hipSuccess;
+        ok &= hipMemcpyAsync(d.merges, merges0.data(), h * 4, hipMemcpyHostToDevice, st) == hipSuccess;
+        ok &= hipMemsetAsync(d.done, 0, h * 4, st) == hipSuccess;
+        ok &= hipMemsetAsync(d.H, 0, h * WB * hi.m * 4, st) == hipSuccess;
+        ok &= hipMemsetAsync(d.base, 0, h * WB * 8, st) == hipSuccess;
+        ok &= hipMemsetAsync(d.flat, 0, S, st) == hipSuccess;
+        ok &= hipMemsetAsync(d.swaps, 0xff, S, st) == hipSuccess;
+        ok &= hipMemsetAsync(d.ex_prop, 0, h * 8, st) == hipSuccess;
+        ok &= hipMemsetAsync(d.ex_acc, 0, h * 8, st) == hipSuccess;
+        ok &= hipStreamSynchronize(st) == hipSuccess;   // host vectors above are locals
+        if (!ok) return bail(fail(REWL_E_DEVICE, "initial upload failed"));
+
+        for (int a = 0; a < hi.h; ++a) {
+            merges.push_back(make_int2(i, a));
+            for (int r0 = 0; r0 < hi.m; r0 += wpb) tiles.push_back({i, a, r0, wpb});
+        }
+        const int64_t work = c.exchange_interval * (int64_t)S;
+        const int64_t nb = std::min<int64_t>(std::max<int64_t>((work + 2047) / 2048, 1), 16384);
+        rng_start.push_back(rng_start.back() + (int32_t)nb);
+        exch_start.push_back(exch_start.back() + ((c.exchange_enabled && hi.h > 1) ? (hi.h - 1) * hi.m : 0));
+        slot_start.push_back(slot_start.back() + hi.S);
+    }
+    rewl_status s = H->alloc(&H->d_ctr, n);
+    if (s != REWL_OK) return bail(s);
+    if (hipHostMalloc((void**)&H->h_ctr, sizeof(InstCtr) * n, hipHostMallocDefault) != hipSuccess)
+        return bail(fail(REWL_E_NOMEM, "hipHostMalloc failed"));
+    if (hipMemsetAsync(H->d_ctr, 0, sizeof(InstCtr) * n, H->stream) != hipSuccess)
+        return bail(fail(REWL_E_DEVICE, "memset failed"));
+    for (int i = 0; i < n; ++i) {
+        H->inst[i].dev.ctr = H->d_ctr + i;
+        devs[i] = H->inst[i].dev;
+    }
+    H->ntiles = (int)tiles.size();
+    H->nmerge = (int)merges.size();
+    H->rng_grid = rng_start.back();
+    H->exch_threads = exch_start.back();
+    H->slot_threads = slot_start.back();
+    if ((s = H->alloc(&H->d_insts, n)) != REWL_OK) return bail(s);
+    if ((s = H->alloc(&H->d_tiles, tiles.size())) != REWL_OK) return bail(s);
+    if ((s = H->alloc(&H->d_merge, merges.size())) != REWL_OK) return bail(s);
+    if ((s = H->alloc(&H->d_rng_start, rng_start.size())) != REWL_OK) return bail(s);
+    if ((s = H->alloc(&H->d_exch_start, exch_start.size())) != REWL_OK) return bail(s);
+    if ((s = H->alloc(&H->d_slot_start, slot_start.size())) != REWL_OK) return bail(s);
+    bool ok = true;
+    hipStream_t st = H->stream;
+    ok &= hipMemcpyAsync(H->d_insts, devs.data(), sizeof(Inst) * n, hipMemcpyHostToDevice, st) == hipSuccess;
+    ok &= hipMemcpyAsync(H->d_tiles, tiles.data(), sizeof(Tile) * tiles.size(), hipMemcpyHostToDevice, st) == hipSuccess;
+    ok &= hipMemcpyAsync(H->d_merge, merges.data(), sizeof(int2) * merges.size(), hipMemcpyHostToDevice, st) == hipSuccess;
+    ok &= hipMemcpyAsync(H->d_rng_start, rng_start.data(), 4 * rng_start.size(), hipMemcpyHostToDevice, st) == hipSuccess;
+    ok &= hipMemcpyAsync(H->d_exch_start, exch_start.data(), 4 * exch_start.size(), hipMemcpyHostToDevice, st) == hipSuccess;
+    ok &= hipMemcpyAsync(H->d_slot_start, slot_start.data(), 4 * slot_start.size(), hipMemcpyHostToDevice, st) == hipSuccess;
+    ok &= hipStreamSynchronize(st) == hipSuccess;
+    if (!ok) return bail(fail(REWL_E_DEVICE, "descriptor upload failed"));
+    if (hipFuncSetAttribute((const void*)k_sweep, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)H->max_lds) != hipSuccess)
+        return bail(fail(REWL_E_DEVICE, "cannot raise the dynamic LDS limit"));
+
+    hipLaunchKernelGGL(k_init, dim3((H->slot_threads + 127) / 128), dim3(128), 0, st, H->d_insts,
+                       H->d_slot_start, n);
+    if (hipGetLastError() != hipSuccess) return bail(fail(REWL_E_DEVICE, "init launch failed"));
+    s = sync_flags(H, nullptr);
+    if (s != REWL_OK) return bail(s);
+    *out = H;
+    return REWL_OK;
+}
+
+rewl_status rewl_batch_create(const rewl_config* cfgs, int32_t n, void* hip_stream,
+                              const rewl_tune* tune, rewl_handle** out)
+{
+    return create_impl(cfgs, n, hip_stream, tune, out);
+}
+
+rewl_status rewl_create(const rewl_config* cfg, void* hip_stream, rewl_handle** out)
+{
+    return create_impl(cfg, 1, hip_stream, nullptr, out);
+}
+
+rewl_status rewl_set_initial_lng(rewl_handle* H, int32_t i, const double* lng)
+{
+    rewl_status s = check_inst(H, i);
+    if (s != REWL_OK) return s;
+    if (!lng) return fail(REWL_E_INVALID, "null table");
+    if (H->started) return fail(REWL_E_STATE, "warm start must precede the first interval");
+    HostInst& hi = H->inst[i];
+    for (int b = 0; b < hi.W; ++b) {
+        const double v = lng[b];
+        if (!std::isfinite(v) || std::fabs(v) >= 0x1p30 || std::ldexp(v, 20) != std::nearbyint(std::ldexp(v, 20)))
+            return fail(REWL_E_INVALID, "warm-start values must be finite multiples of 2^-20 below 2^30");
+    }
+    std::vector<double> tab((size_t)hi.h * hi.WB);
+    for (int a = 0; a < hi.h; ++a)
+        for (int b = 0; b < hi.WB; ++b) tab[(size_t)a * hi.WB + b] = lng[hi.lo[a] + b];
+    HIP_TRY(hipMemcpyAsync(hi.dev.base, tab.data(), tab.size() * 8, hipMemcpyHostToDevice, H->stream));
+    HIP_TRY(hipStreamSynchronize(H->stream));
+    return REWL_OK;
+}
+
+rewl_status rewl_run(rewl_handle* H, int64_t max_intervals, int32_t* all_done)
+{
+    if (!H) return fail(REWL_E_INVALID, "null handle");
+    if (max_intervals < 0) return fail(REWL_E_INVALID, "negative interval count");
+    bool all = false;
+    rewl_status s = sync_flags(H, &all);
+    if (s != REWL_OK) return s;
+    int64_t left = max_intervals;
+    while (!all && left > 0) {
+        const int64_t chunk = std::min<int64_t>(left, H->tune.poll_every);
+        for (int64_t c = 0; c < chunk; ++c)
+            if ((s = step(H)) != REWL_OK) return s;
+        H->started = true;
+        left -= chunk;
+        if ((s = sync_flags(H, &all)) != REWL_OK) return s;
+    }
+    if (all_done) *all_done = all ? 1 : 0;
+    return REWL_OK;
+}
+
+rewl_status rewl_run_exact(rewl_handle* H, int64_t n)
+{
+    if (!H) return fail(REWL_E_INVALID, "null handle");
+    rewl_status s;
+    for (int64_t c = 0; c < n; ++c)
+        if ((s = step(H)) != REWL_OK) return s;
+    if (n > 0) H->started = true;
+    return sync_flags(H, nullptr);
+}
+
+rewl_status rewl_set_timing(rewl_handle* H, int32_t on)
+{
+    if (!H) return fail(REWL_E_INVALID, "null handle");
+    H->timing = on != 0;
+    return REWL_OK;
+}
+
+rewl_status rewl_info(rewl_handle* H, int32_t i, int32_t* n_instances, int32_t* wpb, size_t* lds)
+{
+    rewl_status s = check_inst(H, i);
+    if (s != REWL_OK) return s;
+    if (n_instances) *n_instances = H->n;
+    if (wpb) *wpb = H->inst[i].wpb;
+    if (lds) *lds = H->inst[i].lds;
+    return REWL_OK;
+}
+
+rewl_status rewl_get_window_lng(rewl_handle* H, int32_t i, int32_t a, double* out)
+{
+    rewl_status s = check_inst(H, i);
+    if (s != REWL_OK) return s;
+    HostInst& hi = H->inst[i];
+    if (a < 0 || a >= hi.h || !out) return fail(REWL_E_INVALID, "bad window or null output");
+    HIP_TRY(hipMemcpyAsync(out, hi.dev.base + (size_t)a * hi.WB, hi.WB * 8, hipMemcpyDeviceToHost, H->stream));
+    HIP_TRY(hipStreamSynchronize(H->stream));
+    return REWL_OK;
+}
+
+rewl_status rewl_get_state(rewl_handle* H, int32_t i, uint8_t* spins, int32_t* bins, int64_t* Hout,
+                           double* lng, uint8_t* flat, int32_t* k, uint8_t* done, int8_t* swaps,
+                           int64_t* t)
+{
+    rewl_status s = check_inst(H, i);
+    if (s != REWL_OK) return s;
+    HostInst& hi = H->inst[i];
+    const Inst& d = hi.dev;
+    const size_t S = hi.S, h = hi.h, WB = hi.WB, m = hi.m;
+    hipStream_t st = H->stream;
+    std::vector<int32_t> kk(h), dd(h);
+    HIP_TRY(hipMemcpyAsync(kk.data(), d.k, h * 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(dd.data(), d.done, h * 4, hipMemcpyDeviceToHost, st));
+    std::vector<uint32_t> Hd;
+    std::vector<double> base;
+    if (Hout || lng) {
+        Hd.resize(h * WB * m);
+        base.resize(h * WB);
+        HIP_TRY(hipMemcpyAsync(Hd.data(), d.H, Hd.size() * 4, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(base.data(), d.base, base.size() * 8, hipMemcpyDeviceToHost, st));
+    }
+    std::vector<uint64_t> lat;
+    std::vector<uint8_t> plat;
+    if (spins) {
+        if (d.model == 0) {
+            lat.resize((size_t)hi.cfg.L * hi.wpr * S);
+            HIP_TRY(hipMemcpyAsync(lat.data(), d.lat, lat.size() * 8, hipMemcpyDeviceToHost, st));
+        } else {
+            plat.resize((size_t)hi.N * S);
+            HIP_TRY(hipMemcpyAsync(plat.data(), d.plat, plat.size(), hipMemcpyDeviceToHost, st));
+        }
+    }
+    if (bins) HIP_TRY(hipMemcpyAsync(bins, d.bin, S * 4, hipMemcpyDeviceToHost, st));
+    if (flat) HIP_TRY(hipMemcpyAsync(flat, d.flat, S, hipMemcpyDeviceToHost, st));
+    if (swaps) HIP_TRY(hipMemcpyAsync(swaps, d.swaps, S, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(H->h_ctr, H->d_ctr, sizeof(InstCtr) * H->n, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (k) std::copy(kk.begin(), kk.end(), k);
+    if (done)
+        for (size_t a = 0; a < h; ++a) done[a] = (uint8_t)dd[a];
+    if (t) *t = H->h_ctr[i].t;
+    const int L = hi.cfg.L, N = hi.N;
+    if (spins) {
+        for (size_t sl = 0; sl < S; ++sl)
+            for (int y = 0; y < L; ++y)
+                for (int x = 0; x < L; ++x) {
+                    uint8_t v;
+                    if (d.model == 0)
+                        v = (uint8_t)((lat[(size_t)(y * hi.wpr + (x >> 6)) * S + sl] >> (x & 63)) & 1u);
+                    else
+                        v = plat[(size_t)(y * L + x) * S + sl];
+                    spins[sl * N + y * L + x] = v;
+                }
+    }
+    if (Hout || lng) {
+        for (size_t sl = 0; sl < S; ++sl) {
+            const size_t a = sl / m, r = sl % m;
+            const double scale = std::ldexp(1.0, -kk[a]);
+            for (size_t b = 0; b < WB; ++b) {
+                const uint32_t hv = Hd[(a * WB + b) * m + r];
+                if (Hout) Hout[sl * WB + b] = hv;
+                if (lng) lng[sl * WB + b] = std::fma((double)hv, scale, base[a * WB + b]);
+            }
+        }
+    }
+    return REWL_OK;
+}
+
+rewl_status rewl_get_stats(rewl_handle* H, int32_t i, rewl_stats* out, int64_t* ex_prop, int64_t* ex_acc)
+{
+    rewl_status s = check_inst(H, i);
+    if (s != REWL_OK) return s;
+    HostInst& hi = H->inst[i];
+    std::vector<int32_t> kk(hi.h);
+    HIP_TRY(hipMemcpyAsync(kk.data(), hi.dev.k, hi.h * 4, hipMemcpyDeviceToHost, H->stream));
+    if (ex_prop) HIP_TRY(hipMemcpyAsync(ex_prop, hi.dev.ex_prop, hi.h * 8, hipMemcpyDeviceToHost, H->stream));
+    if (ex_acc) HIP_TRY(hipMemcpyAsync(ex_acc, hi.dev.ex_acc, hi.h * 8, hipMemcpyDeviceToHost, H->stream));
+    HIP_TRY(hipMemcpyAsync(H->h_ctr, H->d_ctr, sizeof(InstCtr) * H->n, hipMemcpyDeviceToHost, H->stream));
+    HIP_TRY(hipStreamSynchronize(H->stream));
+    if (out) {
+        const InstCtr& c = H->h_ctr[i];
+        out->intervals = c.t;
+        out->attempts = c.t * hi.cfg.exchange_interval * (int64_t)hi.S;
+        out->windows_done = c.n_done;
+        out->min_k = *std::min_element(kk.begin(), kk.end());
+        out->sweep_ms = H->sweep_ms;
+        out->interval_ms = H->interval_ms;
+    }
+    return REWL_OK;
+}
+
+rewl_status rewl_concat(rewl_handle* H, int32_t i, double* out_lng, int32_t* join)
+{
+    rewl_status s = check_inst(H, i);
+    if (s != REWL_OK) return s;
+    if (!out_lng) return fail(REWL_E_INVALID, "null output");
+    HostInst& hi = H->inst[i];
+    double *d_out = nullptr, *d_shift = nullptr;
+    int32_t *d_join = nullptr, *d_status = nullptr;
+    HIP_TRY(hipMalloc(&d_out, hi.W * 8));
+    HIP_TRY(hipMalloc(&d_shift, hi.h * 8));
+    HIP_TRY(hipMalloc(&d_join, std::max(hi.h - 1, 1) * 4));
+    HIP_TRY(hipMalloc(&d_status, 4));
+    hipLaunchKernelGGL(k_concat, dim3(1), dim3(256), 0, H->stream, H->d_insts, i, hi.dev.base, d_out,
+                       d_join, d_shift, d_status);
+    int32_t status = 0;
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(out_lng, d_out, hi.W * 8, hipMemcpyDeviceToHost, H->stream);
+    if (e == hipSuccess && join && hi.h > 1)
+        e = hipMemcpyAsync(join, d_join, (hi.h - 1) * 4, hipMemcpyDeviceToHost, H->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&status, d_status, 4, hipMemcpyDeviceToHost, H->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(H->stream);
+    (void)hipFree(d_out);
+    (void)hipFree(d_shift);
+    (void)hipFree(d_join);
+    (void)hipFree(d_status);
+    if (e != hipSuccess) return fail(REWL_E_DEVICE, std::string("concat: ") + hipGetErrorString(e));
+    if (status != 0) return fail(REWL_E_STATE, "no valid join point in some overlap");
+    return REWL_OK;
+}
+
+
+rewl_status rewl_checkpoint(rewl_handle* H, void* buf, size_t* len)
+{
+    if (!H || !len) return fail(REWL_E_INVALID, "null argument");
+    size_t total = 16;
+    for (int i = 0; i < H->n; ++i)
+        for (const Span& sp : spans_of(H, i)) total += sp.bytes;
+    if (!buf) {
+        *len = total;
+        return REWL_OK;
+    }
+    if (*len < total) return fail(REWL_E_INVALID, "checkpoint buffer too small");
+    char* p = (char*)buf;
+    const uint64_t magic = 0x4c57455231ull, count = (uint64_t)H->n;
+    std::memcpy(p, &magic, 8);
+    std::memcpy(p + 8, &count, 8);
+    p += 16;
+    for (int i = 0; i < H->n; ++i)
+        for (const Span& sp : spans_of(H, i)) {
+            HIP_TRY(hipMemcpyAsync(p, sp.dev, sp.bytes, hipMemcpyDeviceToHost, H->stream));
+            p += sp.bytes;
+        }
+    HIP_TRY(hipStreamSynchronize(H->stream));
+    *len = total;
+    return REWL_OK;
+}
+
+rewl_status rewl_restore(rewl_handle* H, const void* buf, size_t len)
+{
+    if (!H || !buf) return fail(REWL_E_INVALID, "null argument");
+    size_t total = 16;
+    for (int i = 0; i < H->n; ++i)
+        for (const Span& sp : spans_of(H, i)) total += sp.bytes;
+    uint64_t magic = 0, count = 0;
+    if (len != total) return fail(REWL_E_INVALID, "checkpoint size does not match this handle");
+    std::memcpy(&magic, buf, 8);
+    std::memcpy(&count, (const char*)buf + 8, 8);
+    if (magic != 0x4c57455231ull || count != (uint64_t)H->n) return fail(REWL_E_INVALID, "not a checkpoint of this batch");
+    const char* p = (const char*)buf + 16;
+    for (int i = 0; i < H->n; ++i)
+        for (const Span& sp : spans_of(H, i)) {
+            HIP_TRY(hipMemcpyAsync(sp.dev, p, sp.bytes, hipMemcpyHostToDevice, H->stream));
+            p += sp.bytes;
+        }
+    HIP_TRY(hipStreamSynchronize(H->stream));
+    H->started = true;
+    return REWL_OK;
+}
+
+rewl_status rewl_probe_accept(const double* delta, const uint64_t* u53, int32_t n, int32_t* out)
+{
+    if (!delta || !u53 || !out || n < 0) return fail(REWL_E_INVALID, "bad arguments");
+    if (n == 0) return REWL_OK;
+    double* dd = nullptr;
+    uint64_t* du = nullptr;
+    int32_t* dout = nullptr;
+    HIP_TRY(hipMalloc(&dd, n * 8));
+    HIP_TRY(hipMalloc(&du, n * 8));
+    HIP_TRY(hipMalloc(&dout, n * 4));
+    hipError_t e = hipMemcpy(dd, delta, n * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(du, u53, n * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_accept_probe, dim3((n + 255) / 256), dim3(256), 0, 0, dd, du, n, dout);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpy(out, dout, n * 4, hipMemcpyDeviceToHost);
+    (void)hipFree(dd);
+    (void)hipFree(du);
+    (void)hipFree(dout);
+    if (e != hipSuccess) return fail(REWL_E_DEVICE, hipGetErrorString(e));
+    return REWL_OK;
+}
+
+rewl_status rewl_probe_philox(const uint32_t* in, int32_t n, uint32_t* out)
+{
+    if (!in || !out || n < 0) return fail(REWL_E_INVALID, "bad arguments");
+    if (n == 0) return REWL_OK;
+    uint32_t *din = nullptr, *dout = nullptr;
+    HIP_TRY(hipMalloc(&din, (size_t)n * 24));
+    HIP_TRY(hipMalloc(&dout, (size_t)n * 16));
+    hipError_t e = hipMemcpy(din, in, (size_t)n * 24, hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_philox_probe, dim3((n + 255) / 256), dim3(256), 0, 0, din, n, dout);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpy(out, dout, (size_t)n * 16, hipMemcpyDeviceToHost);
+    (void)hipFree(din);
+    (void)hipFree(dout);
+    if (e != hipSuccess) return fail(REWL_E_DEVICE, hipGetErrorString(e));
+    return REWL_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,661 @@
+// rewl_kernels.hip -- the REWL hot path on gfx950.
+//
+// One interval of replica-exchange Wang-Landau (arXiv:1407.5140 Sec. II.A):
+//   k_rng      Philox draws of every flip attempt of the interval (whole GPU)
+//   k_sweep    X single-site attempts per walker, one walker per lane, the
+//              walker's lattice and histogram and its window's ln g base in LDS,
+//              flatness test of every walker in the epilogue
+//   k_merge    per window: when all m walkers are flat, average ln g, reset H,
+//              halve ln f, detect convergence
+//   k_exchange Eq. (1) between neighbouring windows, alternating pairings
+//   k_advance  interval counter and termination bookkeeping
+// All interval state lives in device memory, so an interval is a fixed
+// sequence of launches that can be captured once and replayed.
+#include "rewl_device.hpp"
+
+namespace rewl {
+
+// --------------------------------------------------------------------- RNG
+// For instance i, entries e = j*S + slot, j < X.  pack = row | col<<8 | off<<16
+// where site = floor(x0 N / 2^32), row = site / L, col = site % L, and the
+// Potts proposal offset off = floor(x1 (q-1) / 2^32); v = log(u53 2^-53).
+__global__ void __launch_bounds__(256) k_rng(const Inst* __restrict__ insts,
+                                             const int32_t* __restrict__ block_start, int n_inst)
+{
+    int lo = 0, hi = n_inst - 1;
+    const int b = blockIdx.x;
+    while (lo < hi) {                          // instance owning this block
+        int mid = (lo + hi + 1) >> 1;
+        if (block_start[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    const Inst& I = insts[lo];
+    if (I.ctr->all_done) return;
+    const int64_t n = I.X * I.S;
+    const int64_t nthreads = (int64_t)(block_start[lo + 1] - block_start[lo]) * blockDim.x;
+    const int64_t t = I.ctr->t;
+    const uint64_t T0 = (uint64_t)t * (uint64_t)I.X;
+    const uint32_t N = I.N, L = I.L, qm1 = I.q - 1;
+    for (int64_t e = (int64_t)(b - block_start[lo]) * blockDim.x + threadIdx.x; e < n; e += nthreads) {
+        const int64_t j = e / I.S;
+        const uint32_t slot = (uint32_t)(e - j * I.S);
+        const u32x4 x = draw(I.k0, I.k1, T0 + (uint64_t)j, slot, kTagFlip);
+        const uint32_t site = (uint32_t)(((uint64_t)x.x * N) >> 32);
+        const uint32_t row = site / L, col = site - row * L;
+        const uint32_t off = I.model ? (uint32_t)(((uint64_t)x.y * qm1) >> 32) : 0u;
+        I.rpack[e] = row | (col << 8) | (off << 16);
+        I.rv[e] = log_uniform(u53_of(x));
+    }
+}
+
+// ------------------------------------------------------------------- sweep
+struct SweepLds {
+    double* base;     // [WB]
+    uint32_t* H;      // [WB][nw]
+    uint8_t* mask;    // [WB]
+    void* lat;        // Ising [L*wpr][nw] u64, Potts [N][nw] u8
+};
+
+__device__ __forceinline__ size_t align8(size_t v) { return (v + 7) & ~size_t(7); }
+
+__host__ __device__ inline size_t sweep_lds_bytes(int model, int L, int wpr, int WB, int nw)
+{
+    size_t s = (size_t)WB * 8 + (size_t)WB * nw * 4;
+    s = (s + WB + 7) & ~size_t(7);
+    s += model == 0 ? (size_t)L * wpr * nw * 8 : (size_t)L * L * nw;
+    return s;
+}
+
+// Exact acceptance for the lanes whose fast test fell inside the guard band:
+// re-draw the attempt's u53 from its Philox counter and decide exactly.
+__device__ __noinline__ bool slow_decide(const Inst& I, uint64_t T, uint32_t slot, double delta)
+{
+    return accept_slow(delta, u53_of(draw(I.k0, I.k1, T, slot, kTagFlip)));
+}
+
+// Ising, bit-packed rows (WPR words of 64 bits per row).
+template <int WPR>
+__device__ __forceinline__ int ising_aligned(const uint64_t* lat, int nw, int lane, int L, int r,
+                                             int c, int& word_idx, uint64_t& word, int& bit)
+{
+    const int ru = r == 0 ? L - 1 : r - 1;
+    const int rd = r == L - 1 ? 0 : r + 1;
+    const int cl = c == 0 ? L - 1 : c - 1;
+    const int cr = c == L - 1 ? 0 : c + 1;
+    if (WPR == 1) {
+        word_idx = r;
+        word = lat[r * nw + lane];
+        const uint64_t wu = lat[ru * nw + lane];
+        const uint64_t wd = lat[rd * nw + lane];
+        bit = c;
+        const uint32_t s = (uint32_t)(word >> c) & 1u;
+        const uint32_t diff = ((uint32_t)(wu >> c) & 1u) + ((uint32_t)(wd >> c) & 1u) +
+                              ((uint32_t)(word >> cl) & 1u) + ((uint32_t)(word >> cr) & 1u);
+        // aligned neighbours: s=1 -> count of ones, s=0 -> count of zeros
+        return s ? (int)diff : 4 - (int)diff;
+    } else {
+        auto spin = [&](int rr, int cc) -> uint32_t {
+            return (uint32_t)(lat[(rr * WPR + (cc >> 6)) * nw + lane] >> (cc & 63)) & 1u;
+        };
+        word_idx = r * WPR + (c >> 6);
+        word = lat[word_idx * nw + lane];
+        bit = c & 63;
+        const uint32_t s = (uint32_t)(word >> bit) & 1u;
+        const uint32_t ones = spin(ru, c) + spin(rd, c) + spin(r, cl) + spin(r, cr);
+        return s ? (int)ones : 4 - (int)ones;
+    }
+}
+
+template <int MODEL, int WPR>
+__device__ void sweep_tile(const Inst& I, const Tile& tile, char* smem)
+{
+    const int a = tile.window, nw = tile.nw, lane = threadIdx.x;
+    const int WB = I.WB, L = I.L, S = I.S;
+    const int slot0 = a * I.m + tile.r0;
+    const int lo = I.lo[a];
+    SweepLds lds;
+    lds.base = (double*)smem;
+    lds.H = (uint32_t*)(lds.base + WB);
+    lds.mask = (uint8_t*)(lds.H + (size_t)WB * nw);
+    lds.lat = (void*)(smem + align8((size_t)WB * 8 + (size_t)WB * nw * 4 + WB));
+    const int nthr = blockDim.x;
+    const int lnw = __builtin_ctz(nw);            // nw is a power of two
+
+    // ---- stage the window table, the tile's histograms and lattices in LDS
+    for (int i = lane; i < WB; i += nthr) {
+        lds.base[i] = I.base[(size_t)a * WB + i];
+        lds.mask[i] = I.mask[lo + i];
+    }
+    for (int i = lane; i < WB * nw; i += nthr) {
+        const int b = i >> lnw, l = i & (nw - 1);
+        lds.H[i] = I.H[((size_t)a * WB + b) * I.m + tile.r0 + l];
+    }
+    if (MODEL == 0) {
+        uint64_t* lat = (uint64_t*)lds.lat;
+        const int nwords = L * WPR;
+        for (int i = lane; i < nwords * nw; i += nthr) {
+            const int w = i >> lnw, l = i & (nw - 1);
+            lat[i] = I.lat[(size_t)w * S + slot0 + l];
+        }
+    } else {
+        uint8_t* lat = (uint8_t*)lds.lat;
+        for (int i = lane; i < I.N * nw; i += nthr) {
+            const int w = i >> lnw, l = i & (nw - 1);
+            lat[i] = I.plat[(size_t)w * S + slot0 + l];
+        }
+    }
+    __syncthreads();
+
+    const int k = I.k[a];
+    const bool upd = I.done[a] == 0;
+    const double scale = __builtin_ldexp(1.0, -k);
+    const int64_t X = I.X;
+    const uint64_t T0 = (uint64_t)I.ctr->t * (uint64_t)X;
+    const int wmax = WB - 1;
+
+    if (lane < nw) {
+        const int slot = slot0 + lane;
+        int b = I.bin[slot] - lo;
+        uint32_t hc = lds.H[(b << lnw) + lane];
+        double bc = lds.base[b];
+        double lngc = __builtin_fma((double)hc, scale, bc);
+        const uint32_t* __restrict__ rp = I.rpack + slot;
+        const double* __restrict__ rvp = I.rv + slot;
+        uint32_t pk_next = rp[0];
+        double v_next = rvp[0];
+        for (int64_t j = 0; j < X; ++j) {
+            const uint32_t pk = pk_next;
+            const double v = v_next;
+            if (j + 1 < X) {
+                pk_next = rp[(j + 1) * S];
+                v_next = rvp[(j + 1) * S];
+            }
+            const int r = pk & 0xff, c = (pk >> 8) & 0xff;
+            int nb, widx = 0, bit = 0;
+            uint64_t word = 0;
+            uint8_t newv = 0;
+            int site = 0;
+            if (MODEL == 0) {
+                const int al = ising_aligned<WPR>((const uint64_t*)lds.lat, nw, lane, L, r, c,
+                                                  widx, word, bit);
+                nb = b + al - 2;                      // dE = 4 al - 8, bin = (E + 2N)/4
+            } else {
+                const uint8_t* lat = (const uint8_t*)lds.lat;
+                site = r * L + c;
+                const int ru = r == 0 ? L - 1 : r - 1, rd = r == L - 1 ? 0 : r + 1;
+                const int cl = c == 0 ? L - 1 : c - 1, cr = c == L - 1 ? 0 : c + 1;
+                const int s0 = lat[(site << lnw) + lane];
+                const int n0 = lat[((ru * L + c) << lnw) + lane];
+                const int n1 = lat[((rd * L + c) << lnw) + lane];
+                const int n2 = lat[((r * L + cl) << lnw) + lane];
+                const int n3 = lat[((r * L + cr) << lnw) + lane];
+                int nv = s0 + 1 + (int)(pk >> 16);
+                nv = nv >= I.q ? nv - I.q : nv;
+                newv = (uint8_t)nv;
+                const int nold = (n0 == s0) + (n1 == s0) + (n2 == s0) + (n3 == s0);
+                const int nnew = (n0 == nv) + (n1 == nv) + (n2 == nv) + (n3 == nv);
+                nb = b + nold - nnew;                 // dE = n(old) - n(new), bin = E + 2N
+            }
+            const bool inwin = (unsigned)nb <= (unsigned)wmax;
+            const int nbc = inwin ? nb : b;
+            const double bn = lds.base[nbc];
+            uint32_t hn = lds.H[(nbc << lnw) + lane];
+            hn = nbc == b ? hc : hn;
+            const double lngn = __builtin_fma((double)hn, scale, bn);
+            const double delta = lngc - lngn;         // exact
+            int f = inwin ? accept_fast(delta, v) : 0;
+            if (__any(f == 2)) {
+                if (f == 2) f = slow_decide(I, T0 + (uint64_t)j, (uint32_t)slot, delta) ? 1 : 0;
+            }
+            if (f) {
+                if (nb != b) {
+                    lds.H[(b << lnw) + lane] = hc;
+                    hc = hn;
+                    bc = bn;
+                    b = nb;
+                }
+                if (MODEL == 0)
+                    ((uint64_t*)lds.lat)[(widx << lnw) + lane] = word ^ (1ull << bit);
+                else
+                    ((uint8_t*)lds.lat)[(site << lnw) + lane] = newv;
+            }
+            hc += upd ? 1u : 0u;
+            lngc = __builtin_fma((double)hc, scale, bc);
+        }
+        lds.H[(b << lnw) + lane] = hc;
+        I.bin[slot] = b + lo;
+        I.swaps[slot] = -1;
+    }
+    __syncthreads();
+
+    // ---- write back
+    for (int i = lane; i < WB * nw; i += nthr) {
+        const int bb = i >> lnw, l = i & (nw - 1);
+        I.H[((size_t)a * WB + bb) * I.m + tile.r0 + l] = lds.H[i];
+    }
+    if (MODEL == 0) {
+        const uint64_t* lat = (const uint64_t*)lds.lat;
+        for (int i = lane; i < L * WPR * nw; i += nthr) {
+            const int w = i >> lnw, l = i & (nw - 1);
+            I.lat[(size_t)w * S + slot0 + l] = lat[i];
+        }
+    } else {
+        const uint8_t* lat = (const uint8_t*)lds.lat;
+        for (int i = lane; i < I.N * nw; i += nthr) {
+            const int w = i >> lnw, l = i & (nw - 1);
+            I.plat[(size_t)w * S + slot0 + l] = lat[i];
+        }
+    }
+
+    // ---- flatness of each walker (Sec. II.A): min H >= num/den * mean H over
+    //      the levels of the window that occur; latched until the window merges
+    if (upd && lane < nw) {
+        uint32_t mn = 0xffffffffu;
+        uint64_t sum = 0;
+        for (int bb = 0; bb < WB; ++bb) {
+            if (!lds.mask[bb]) continue;
+            const uint32_t v = lds.H[(bb << lnw) + lane];
+            mn = v < mn ? v : mn;
+            sum += v;
+        }
+        const int slot = slot0 + lane;
+        const int64_t n = I.nreach[a];
+        if ((int64_t)I.flat_den * (int64_t)mn * n >= (int64_t)I.flat_num * (int64_t)sum)
+            I.flat[slot] = 1;
+        if (sum + (uint64_t)X >= 0xffffffffull) atomicOr(&I.ctr->err, kErrOverflow);
+    }
+}
+
+__global__ void __launch_bounds__(64) k_sweep(const Inst* __restrict__ insts,
+                                              const Tile* __restrict__ tiles, int ntiles)
+{
+    extern __shared__ __align__(16) char smem[];
+    const Tile tile = tiles[blockIdx.x];
+    const Inst& I = insts[tile.inst];
+    if (I.ctr->all_done) return;
+    if (I.model == 0) {
+        if (I.wpr == 1) sweep_tile<0, 1>(I, tile, smem);
+        else sweep_tile<0, 2>(I, tile, smem);
+    } else {
+        sweep_tile<1, 1>(I, tile, smem);
+    }
+}
+
+// ------------------------------------------------------------------- merge
+// One block per (instance, window).  When all m walkers are flat:
+// ln g := mean_w ln g_w = base + 2^-(k + log2 m) sum_w H_w (exact), then the
+// table is shifted by the integer part of its minimum over occurring levels.
+__global__ void __launch_bounds__(256) k_merge(const Inst* __restrict__ insts,
+                                               const int2* __restrict__ items)
+{
+    __shared__ double red[256];
+    __shared__ int okflag, skip;
+    const int2 it = items[blockIdx.x];
+    const Inst& I = insts[it.x];
+    const int a = it.y, tid = threadIdx.x;
+    if (tid == 0) skip = I.ctr->all_done || I.done[a];   // one read, block-uniform
+    __syncthreads();
+    if (skip) return;
+    int ok = 1;
+    for (int r = tid; r < I.m; r += blockDim.x) ok &= I.flat[a * I.m + r];
+    ok = __syncthreads_and(ok);
+    if (!ok) return;
+    const int WB = I.WB, m = I.m, k = I.k[a], lo = I.lo[a];
+    const int sh = k + I.log2m;
+    double* base = I.base + (size_t)a * WB;
+    uint32_t* H = I.H + (size_t)a * WB * m;
+    double mn = __builtin_inf(), mx = 0.0;
+    for (int b = tid; b < WB; b += blockDim.x) {
+        uint64_t s = 0;
+        for (int r = 0; r < m; ++r) s += H[(size_t)b * m + r];
+        const double nb = base[b] + __builtin_ldexp((double)s, -sh);
+        base[b] = nb;
+        if (I.mask[lo + b]) mn = nb < mn ? nb : mn;
+        mx = fabs(nb) > mx ? fabs(nb) : mx;
+    }
+    red[tid] = mn;
+    __syncthreads();
+    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+        if (tid < st) red[tid] = red[tid + st] < red[tid] ? red[tid + st] : red[tid];
+        __syncthreads();
+    }
+    const double shift = floor(red[0]);
+    __syncthreads();
+    red[tid] = mx;
+    __syncthreads();
+    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+        if (tid < st) red[tid] = red[tid + st] > red[tid] ? red[tid + st] : red[tid];
+        __syncthreads();
+    }
+    if (tid == 0) okflag = red[0] < __builtin_ldexp(1.0, 52 - sh);
+    __syncthreads();
+    for (int b = tid; b < WB; b += blockDim.x) base[b] = base[b] - shift;
+    for (size_t i = tid; i < (size_t)WB * m; i += blockDim.x) H[i] = 0u;
+    for (int r = tid; r < m; r += blockDim.x) I.flat[a * m + r] = 0;
+    if (tid == 0) {
+        if (!okflag) atomicOr(&I.ctr->err, kErrExactness);
+        I.k[a] = k + 1;
+        I.merges[a] = (int32_t)I.ctr->t;
+        if (k + 1 >= I.kfinal) {
+            I.done[a] = 1;
+            const int nd = atomicAdd(&I.ctr->n_done, 1) + 1;
+            if (nd == I.h) I.ctr->all_done = 1;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- exchange
+// Thread per (instance, window a < h-1, walker r); pairs with a = t (mod 2)
+// are active.  Walker r of window a meets walker (r + c) mod m of window a+1,
+// c drawn once per (t, a).  Eq. (1) in log form, decided exactly; on accept the
+// two configurations (lattice and energy) change places, ln g and H stay.
+__global__ void __launch_bounds__(256) k_exchange(const Inst* __restrict__ insts,
+                                                  const int32_t* __restrict__ thread_start,
+                                                  int n_inst)
+{
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= thread_start[n_inst]) return;
+    int lo_i = 0, hi_i = n_inst - 1;
+    while (lo_i < hi_i) {
+        int mid = (lo_i + hi_i + 1) >> 1;
+        if (thread_start[mid] <= gid) lo_i = mid;
+        else hi_i = mid - 1;
+    }
+    const Inst& I = insts[lo_i];
+    if (!I.exch || I.ctr->all_done) return;
+    const int local = gid - thread_start[lo_i];
+    const int m = I.m, a = local / m, r = local - a * m;
+    const int64_t t = I.ctr->t;
+    if ((a & 1) != (int)(t & 1)) return;
+    const u32x4 xc = draw(I.k0, I.k1, (uint64_t)t, (uint32_t)a, kTagPartner);
+    const int c = (int)(((uint64_t)xc.x * (uint64_t)m) >> 32);
+    const int rj = (r + c) & (m - 1);
+    const int i = a * m + r, j = (a + 1) * m + rj;
+    const int bi = I.bin[i], bj = I.bin[j];
+    const int loa = I.lo[a], hia = I.hi[a], lob = I.lo[a + 1], hib = I.hi[a + 1];
+    bool acc = false;
+    if (bj >= loa && bj <= hia && bi >= lob && bi <= hib) {
+        const int WB = I.WB;
+        const double sa = __builtin_ldexp(1.0, -I.k[a]);
+        const double sb = __builtin_ldexp(1.0, -I.k[a + 1]);
+        const double* ba = I.base + (size_t)a * WB;
+        const double* bb = I.base + (size_t)(a + 1) * WB;
+        const uint32_t* Ha = I.H + (size_t)a * WB * m;
+        const uint32_t* Hb = I.H + (size_t)(a + 1) * WB * m;
+        auto gi = [&](int bin) { return __builtin_fma((double)Ha[(size_t)(bin - loa) * m + r], sa, ba[bin - loa]); };
+        auto gj = [&](int bin) { return __builtin_fma((double)Hb[(size_t)(bin - lob) * m + rj], sb, bb[bin - lob]); };
+        const double delta = (gi(bi) - gi(bj)) + (gj(bj) - gj(bi));
+        acc = accept_full(delta, u53_of(draw(I.k0, I.k1, (uint64_t)t, (uint32_t)i, kTagExchange)));
+    }
+    if (acc) {
+        if (I.model == 0) {
+            const int nwords = I.L * I.wpr;
+            for (int w = 0; w < nwords; ++w) {
+                uint64_t* p = I.lat + (size_t)w * I.S;
+                const uint64_t x = p[i];
+                p[i] = p[j];
+                p[j] = x;
+            }
+        } else {
+            for (int w = 0; w < I.N; ++w) {
+                uint8_t* p = I.plat + (size_t)w * I.S;
+                const uint8_t x = p[i];
+                p[i] = p[j];
+                p[j] = x;
+            }
+        }
+        I.bin[i] = bj;
+        I.bin[j] = bi;
+        atomicAdd((unsigned long long*)&I.ex_acc[a], 1ull);
+    }
+    atomicAdd((unsigned long long*)&I.ex_prop[a], 1ull);
+    I.swaps[i] = acc ? 1 : 0;
+    I.swaps[j] = acc ? 1 : 0;
+}
+
+// ----------------------------------------------------------------- advance
+__global__ void k_advance(const Inst* __restrict__ insts, int n_inst)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_inst) return;
+    InstCtr* c = insts[i].ctr;
+    if (!c->stopped) {
+        c->t += 1;
+        if (c->all_done) c->stopped = 1;
+    }
+    c->queue = 0;
+}
+
+// -------------------------------------------------------------------- init
+// Thread per slot.  Start from a ground state (Ising: all up, or the
+// checkerboard for a window in the upper half; Potts: all 0) and take every
+// proposal that does not increase the distance of the energy bin to the window.
+__device__ int lattice_bin(const Inst& I, int slot)
+{
+    const int L = I.L;
+    int broken = 0;
+    for (int y = 0; y < L; ++y)
+        for (int x = 0; x < L; ++x) {
+            const int xr = x + 1 == L ? 0 : x + 1, yd = y + 1 == L ? 0 : y + 1;
+            if (I.model == 0) {
+                auto sp = [&](int yy, int xx) {
+                    return (int)(I.lat[(size_t)(yy * I.wpr + (xx >> 6)) * I.S + slot] >> (xx & 63)) & 1;
+                };
+                broken += (sp(y, x) != sp(y, xr)) + (sp(y, x) != sp(yd, x));
+            } else {
+                auto sp = [&](int yy, int xx) { return (int)I.plat[(size_t)(yy * L + xx) * I.S + slot]; };
+                broken += (sp(y, x) != sp(y, xr)) + (sp(y, x) != sp(yd, x));
+            }
+        }
+    return I.model == 0 ? broken / 2 : broken;
+}
+
+__global__ void k_init(const Inst* __restrict__ insts, const int32_t* __restrict__ thread_start,
+                       int n_inst)
+{
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= thread_start[n_inst]) return;
+    int lo_i = 0, hi_i = n_inst - 1;
+    while (lo_i < hi_i) {
+        int mid = (lo_i + hi_i + 1) >> 1;
+        if (thread_start[mid] <= gid) lo_i = mid;
+        else hi_i = mid - 1;
+    }
+    const Inst& I = insts[lo_i];
+    const int slot = gid - thread_start[lo_i];
+    const int a = slot / I.m, L = I.L, N = I.N;
+    const int wlo = I.lo[a], whi = I.hi[a];
+    const bool upper = wlo + whi > I.W - 1;
+    if (I.model == 0) {
+        for (int y = 0; y < L; ++y)
+            for (int wi = 0; wi < I.wpr; ++wi) {
+                uint64_t word = 0;
+                for (int xb = 0; xb < 64; ++xb) {
+                    const int x = wi * 64 + xb;
+                    if (x >= L) break;
+                    const bool up = upper ? ((x + y) & 1) == 0 : true;
+                    word |= (uint64_t)up << xb;
+                }
+                I.lat[(size_t)(y * I.wpr + wi) * I.S + slot] = word;
+            }
+    } else {
+        for (int s = 0; s < N; ++s) I.plat[(size_t)s * I.S + slot] = 0;
+    }
+    int b = lattice_bin(I, slot);
+    auto dist = [&](int bb) { return bb < wlo ? wlo - bb : (bb > whi ? bb - whi : 0); };
+    const int64_t cap = 1000 * (int64_t)N;
+    for (int64_t j = 0; b < wlo || b > whi; ++j) {
+        if (j >= cap) {
+            atomicOr(&I.ctr->err, kErrInitStuck);
+            return;
+        }
+        const u32x4 x = draw(I.k0, I.k1, (uint64_t)j, (uint32_t)slot, kTagInit);
+        const int site = (int)(((uint64_t)x.x * (uint64_t)N) >> 32);
+        const int r = site / L, c = site - r * L;
+        const int ru = r == 0 ? L - 1 : r - 1, rd = r == L - 1 ? 0 : r + 1;
+        const int cl = c == 0 ? L - 1 : c - 1, cr = c == L - 1 ? 0 : c + 1;
+        int nb;
+        int nv = 0;
+        if (I.model == 0) {
+            auto sp = [&](int yy, int xx) {
+                return (int)(I.lat[(size_t)(yy * I.wpr + (xx >> 6)) * I.S + slot] >> (xx & 63)) & 1;
+            };
+            const int s = sp(r, c);
+            const int ones = sp(ru, c) + sp(rd, c) + sp(r, cl) + sp(r, cr);
+            const int al = s ? ones : 4 - ones;
+            nb = b + al - 2;
+        } else {
+            auto sp = [&](int yy, int xx) { return (int)I.plat[(size_t)(yy * L + xx) * I.S + slot]; };
+            const int s = sp(r, c);
+            nv = s + 1 + (int)(((uint64_t)x.y * (uint64_t)(I.q - 1)) >> 32);
+            nv = nv >= I.q ? nv - I.q : nv;
+            const int n[4] = {sp(ru, c), sp(rd, c), sp(r, cl), sp(r, cr)};
+            int nold = 0, nnew = 0;
+            for (int d = 0; d < 4; ++d) {
+                nold += n[d] == s;
+                nnew += n[d] == nv;
+            }
+            nb = b + nold - nnew;
+        }
+        if (dist(nb) <= dist(b)) {
+            if (I.model == 0) {
+                uint64_t* p = I.lat + (size_t)(r * I.wpr + (c >> 6)) * I.S + slot;
+                *p ^= 1ull << (c & 63);
+            } else {
+                I.plat[(size_t)site * I.S + slot] = (uint8_t)nv;
+            }
+            b = nb;
+        }
+    }
+    I.bin[slot] = b;
+}
+
+// ------------------------------------------------------------ concatenate
+// Sec. II.B: per overlap, 5-point derivative of both pieces with step d,
+// join where they agree best (ties to the lower bin, joins ascending), shift
+// the pieces, cut the tails, normalise to sum g = q^N.  One block per call.
+__global__ void __launch_bounds__(256) k_concat(const Inst* __restrict__ insts, int inst,
+                                                const double* __restrict__ pieces,
+                                                double* __restrict__ out,
+                                                int32_t* __restrict__ join, double* __restrict__ shift,
+                                                int32_t* __restrict__ status)
+{
+    __shared__ double rd[256];
+    __shared__ int rb[256];
+    const Inst& I = insts[inst];
+    const int h = I.h, WB = I.WB, W = I.W, tid = threadIdx.x;
+    if (tid == 0) {
+        shift[0] = 0.0;
+        *status = 0;
+    }
+    __syncthreads();
+    for (int a = 0; a + 1 < h; ++a) {
+        const double* fa = pieces + (size_t)a * WB;
+        const double* fb = pieces + (size_t)(a + 1) * WB;
+        const int loa = I.lo[a], lob = I.lo[a + 1], hia = I.hi[a];
+        const int ov = hia - lob + 1;
+        int d = ov / 8;
+        d = d < 1 ? 1 : (d > 10 ? 10 : d);
+        int first = lob + 2 * d;
+        if (a > 0 && join[a - 1] + 1 > first) first = join[a - 1] + 1;
+        double best = __builtin_inf();
+        int bestb = -1;
+        for (int b = first + tid; b + 2 * d <= hia; b += blockDim.x) {
+            const uint8_t* mk = I.mask;
+            if (!mk[b] || !mk[b - d] || !mk[b + d] || !mk[b - 2 * d] || !mk[b + 2 * d]) continue;
+            const int ia = b - loa, ib = b - lob;
+            const double na = ((fa[ia - 2 * d] - 8.0 * fa[ia - d]) + 8.0 * fa[ia + d]) - fa[ia + 2 * d];
+            const double nbv = ((fb[ib - 2 * d] - 8.0 * fb[ib - d]) + 8.0 * fb[ib + d]) - fb[ib + 2 * d];
+            const double diff = fabs(na / (12.0 * d) - nbv / (12.0 * d));
+            if (bestb < 0 || diff < best) {
+                best = diff;
+                bestb = b;
+            }
+        }
+        rd[tid] = best;
+        rb[tid] = bestb;
+        __syncthreads();
+        for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+            if (tid < st) {
+                const double d2 = rd[tid + st];
+                const int b2 = rb[tid + st];
+                if (b2 >= 0 && (rb[tid] < 0 || d2 < rd[tid] || (d2 == rd[tid] && b2 < rb[tid]))) {
+                    rd[tid] = d2;
+                    rb[tid] = b2;
+                }
+            }
+            __syncthreads();
+        }
+        if (tid == 0) {
+            const int bs = rb[0];
+            if (bs < 0) {                      // no valid join: report, keep indices inside
+                *status = -2;
+                join[a] = first < lob ? lob : (first > hia ? hia : first);
+                shift[a + 1] = shift[a];
+            } else {
+                join[a] = bs;
+                shift[a + 1] = shift[a] + (fa[bs - loa] - fb[bs - lob]);
+            }
+        }
+        __syncthreads();
+    }
+    // assemble
+    double mx = -__builtin_inf();
+    for (int b = tid; b < W; b += blockDim.x) {
+        int a = 0;
+        while (a + 1 < h && b > join[a]) ++a;
+        const double v = pieces[(size_t)a * WB + (b - I.lo[a])] + shift[a];
+        out[b] = v;
+        if (I.mask[b] && v > mx) mx = v;
+    }
+    rd[tid] = mx;
+    __syncthreads();
+    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+        if (tid < st) rd[tid] = rd[tid + st] > rd[tid] ? rd[tid + st] : rd[tid];
+        __syncthreads();
+    }
+    const double gmax = rd[0];
+    __syncthreads();
+    double acc = 0.0;
+    for (int b = tid; b < W; b += blockDim.x)
+        if (I.mask[b]) acc += exp(out[b] - gmax);
+    rd[tid] = acc;
+    __syncthreads();
+    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+        if (tid < st) rd[tid] += rd[tid + st];
+        __syncthreads();
+    }
+    const double lse = gmax + log(rd[0]);
+    const double target = (double)I.N * log(I.model == 0 ? 2.0 : (double)I.q);
+    __syncthreads();
+    for (int b = tid; b < W; b += blockDim.x)
+        out[b] = I.mask[b] ? out[b] + (target - lse) : -__builtin_inf();
+}
+
+// ------------------------------------------------------ predicate probe
+// Evaluates the full acceptance predicate (fast test against log(u53 2^-53)
+// with the guard band, exact slow path inside it) on caller-given inputs.
+__global__ void k_accept_probe(const double* __restrict__ delta, const uint64_t* __restrict__ u53,
+                               int n, int32_t* __restrict__ out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        const int f = accept_fast(delta[i], log_uniform(u53[i]));
+        out[i] = f == 2 ? (accept_slow(delta[i], u53[i]) ? 3 : 2) : f;
+    }
+}
+
+__global__ void k_philox_probe(const uint32_t* __restrict__ in, int n, uint32_t* __restrict__ out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        const uint32_t* c = in + 6 * i;
+        const u32x4 x = philox10(c[0], c[1], c[2], c[3], c[4], c[5]);
+        out[4 * i + 0] = x.x;
+        out[4 * i + 1] = x.y;
+        out[4 * i + 2] = x.z;
+        out[4 * i + 3] = x.w;
+    }
+}
+
+}  // namespace rewl
