@@ -1,0 +1,153 @@
+"""Throughput of the REWL hot path on one MI355X.
+
+A step is one exchange interval of the whole method (Philox draws, X single-spin
+attempts per walker, flatness/merge, replica exchange, interval bookkeeping) over
+the workload's walkers.  Default workload: 2D Ising L=64 periodic, 16 windows with
+75% overlap, 64 walkers per window (1024 walkers), exchange every 10^4 attempts,
+ln f from 1 to 2^-27, Philox seed 1.
+
+Prints one JSON line: whole-job flip attempts per second, the sweep kernel's
+roofline figures (from HIP events on the library's stream), and the oracle timed on
+the host cores on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Peaks of one MI355X (public figures): 256 CUs x 64 lanes at 2.4 GHz issue
+# 3.93e13 32-bit VALU lane-operations per second (the FP64 vector rate,
+# 78.6 TFLOP/s, is the same lane rate counting an FMA as two flops).
+PEAK_LANE_OPS = 256 * 64 * 2.4e9
+PEAK_HBM = 8.0e12
+
+# Algorithmic lane-operations of one flip attempt inside the sweep (the draws are
+# made by the RNG kernel): Ising bit-packed -- 3 row reads, 5 bit extracts, 4
+# comparisons summed (12); new bin and window test (3); 2 table reads, convert,
+# fused multiply-add (4); delta and the two-sided test against log u (3); the
+# conditional flip, bin/histogram/base bookkeeping (5); histogram increment and
+# ln g update (3).  Potts adds 2 reads and 5 comparisons for the new state.
+OPS_PER_ATTEMPT = {"ising": 30, "potts": 37}
+
+WORKLOADS = {
+    "ising64": dict(model="ising", L=64, n_windows=16, m=64, kfinal=27, X=10000, seed=1,
+                    label="2D Ising L=64 periodic, 16 windows o=3/4, 64 walkers/window, X=1e4"),
+    "potts32": dict(model="potts", q=10, L=32, n_windows=32, m=128, kfinal=27, X=10000, seed=1,
+                    label="2D 10-state Potts L=32 periodic, 32 windows o=3/4, 128 walkers/window, X=1e4"),
+}
+
+
+def _sync():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            torch.cuda.synchronize()
+    except Exception:
+        pass
+
+
+def cpu_baseline(kw: dict, budget_s: float) -> dict:
+    """The oracle as it stands, all host threads, a bounded number of intervals."""
+    import oracle as O
+    cfg = O.make_config(**{k: v for k, v in kw.items() if k != "label"})
+    sim = O.Sim(cfg)
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
+    t0 = time.perf_counter()
+    sim.run(1, threads=threads)
+    one = time.perf_counter() - t0
+    n = max(1, min(200, int(budget_s / max(one, 1e-3))))
+    t0 = time.perf_counter()
+    sim.run(n, threads=threads)
+    dt = time.perf_counter() - t0
+    S = kw["n_windows"] * kw["m"]
+    return {"value": n * S * kw["X"] / dt, "unit": "attempts/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n} exchange intervals ({n * S * kw['X']:.3g} attempts) of the same workload "
+                      f"after 1 warm-up interval, {dt:.1f} s"}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="ising64", choices=sorted(WORKLOADS))
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args(argv)
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is "
+              "described, not built.", file=sys.stderr)
+        return 2
+
+    import paper_1407_5140_amd as rw
+
+    kw = dict(WORKLOADS[args.workload])
+    label = kw.pop("label")
+    cfg = rw.make_config(**kw)
+    S = kw["n_windows"] * kw["m"]
+    X = kw["X"]
+    t_create = time.perf_counter()
+    g = rw.Rewl([cfg])
+    t_create = time.perf_counter() - t_create
+    info = g.info()
+    print(f"[bench] {label}: {S} walkers, walkers/block {info['walkers_per_block']}, "
+          f"LDS {info['lds_bytes']} B, create {t_create:.2f} s", file=sys.stderr, flush=True)
+
+    rw.rewl_run_exact(g.h, args.warmup)
+    rw.rewl_set_timing(g.h, True)
+    st0 = g.stats()
+    _sync()
+    t0 = time.perf_counter()
+    rw.rewl_run_exact(g.h, args.steps)
+    _sync()
+    dt = time.perf_counter() - t0
+    st1 = g.stats()
+    rw.rewl_set_timing(g.h, False)
+    attempts = args.steps * S * X
+    value = attempts / dt
+    sweep_ms = (st1["sweep_ms"] - st0["sweep_ms"]) / args.steps
+    interval_ms = (st1["interval_ms"] - st0["interval_ms"]) / args.steps
+    ops = OPS_PER_ATTEMPT[kw["model"]] * S * X
+    achieved = ops / (sweep_ms * 1e-3)
+    print(f"[bench] {args.steps} intervals in {dt:.3f} s: {value:.4g} attempts/s; sweep "
+          f"{sweep_ms:.3f} ms/launch, interval {interval_ms:.3f} ms (events)", file=sys.stderr,
+          flush=True)
+
+    out = {
+        "metric": "spin-flip attempts/s; time to ln f=1e-8, MLP warm-start vs plain REWL",
+        "value": value,
+        "unit": "attempts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": label, "walkers": S, "attempts_per_step": S * X,
+                   "walkers_per_block": info["walkers_per_block"]},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
+                     "unit": "Tops/s", "frac": achieved / PEAK_LANE_OPS, "traffic": None,
+                     "kernel": "k_sweep", "kernel_ms": sweep_ms,
+                     "ops_per_attempt": OPS_PER_ATTEMPT[kw["model"]]},
+        "sweep_attempts_per_s": S * X / (sweep_ms * 1e-3),
+    }
+    g.close()
+    if not args.no_cpu_baseline:
+        print("[bench] timing the oracle on the host cores", file=sys.stderr, flush=True)
+        kwl = dict(WORKLOADS[args.workload])
+        out["cpu_baseline"] = cpu_baseline(kwl, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -387,6 +387,9 @@ static rewl_status create_impl(const rewl_config* cfgs, int32_t n, void* hip_str
         d.m = hi.m; d.S = hi.S; d.WB = hi.WB; d.log2m = hi.log2m; d.flat_num = c.flat_num;
         d.flat_den = c.flat_den; d.kfinal = c.lnf_kfinal; d.exch = c.exchange_enabled; d.wpr = hi.wpr;
         d.X = c.exchange_interval; d.k0 = (uint32_t)c.seed; d.k1 = (uint32_t)(c.seed >> 32);
+        d.XP = (c.exchange_interval + 31) / 32 * 32;   // two draw chunks of 16
+        if ((uint64_t)d.XP * hi.S >= (uint64_t(1) << 32))
+            return bail(fail(REWL_E_INVALID, "instance " + std::to_string(i) + ": walkers x interval exceeds 2^32 draws"));
         const size_t S = hi.S, h = hi.h, WB = hi.WB;
         rewl_status s = REWL_OK;
         if (c.model == 0) s = H->alloc(&d.lat, (size_t)c.L * hi.wpr * S);
@@ -402,8 +405,8 @@ static rewl_status create_impl(const rewl_config* cfgs, int32_t n, void* hip_str
         if (s == REWL_OK) s = H->alloc(&d.done, h);
         if (s == REWL_OK) s = H->alloc(&d.flat, S);
         if (s == REWL_OK) s = H->alloc(&d.swaps, S);
-        if (s == REWL_OK) s = H->alloc(&d.rpack, (size_t)c.exchange_interval * S);
-        if (s == REWL_OK) s = H->alloc(&d.rv, (size_t)c.exchange_interval * S);
+        if (s == REWL_OK) s = H->alloc(&d.rpack, (size_t)d.XP * S);
+        if (s == REWL_OK) s = H->alloc(&d.rv, (size_t)d.XP * S);
         if (s == REWL_OK) s = H->alloc(&d.ex_prop, h);
         if (s == REWL_OK) s = H->alloc(&d.ex_acc, h);
         if (s == REWL_OK) s = H->alloc(&d.merges, h);

@@ -138,30 +138,28 @@ __device__ inline bool accept_slow(double delta, uint64_t u53)
     return diff < y.lo;
 }
 
-// log(u53 * 2^-53), the threshold the move is compared against (-inf for 0).
-__device__ __forceinline__ double log_uniform(uint64_t u53)
-{
-    return u53 == 0 ? -__builtin_inf() : log(__builtin_ldexp((double)u53, -53));
-}
-
-// Guard band of the fast comparison delta vs log(u): the device log is within a
-// few ulp (|log| <= 36.8, ulp <= 7.2e-15); 2^-40 leaves a margin above 100 ulp.
+// Guard band of the fast comparison: the device log is within a few ulp
+// (|log u| <= 36.8, ulp <= 7.2e-15); 2^-40 leaves a margin above 100 ulp.
 constexpr double kBand = 0x1p-40;
 
-// Fast form of the exact predicate given v = log(u53 2^-53):
-// returns 1 accept, 0 reject, 2 undecided (use accept_slow).
-__device__ __forceinline__ int accept_fast(double delta, double v)
+// Threshold of the fast test for a draw u53: vb = log(u53 2^-53) + band, or
+// -DBL_MAX for u53 = 0 (every finite delta accepts, an out-of-window move with
+// delta = -inf does not).  accept  <=>  delta > log(u53 2^-53)  exactly; the
+// fast test decides whenever delta is outside [vb - 2 band, vb].
+__device__ __forceinline__ double threshold_of(uint64_t u53)
 {
-    if (delta >= 0.0) return 1;
-    double d = delta - v;
-    if (d > kBand) return 1;
-    if (d < -kBand) return 0;
-    return 2;
+    return u53 == 0 ? -0x1.fffffffffffffp+1023 : log(__builtin_ldexp((double)u53, -53)) + kBand;
+}
+
+// 1 accept, 0 reject, 2 undecided (decide with accept_slow).
+__device__ __forceinline__ int decide_fast(double delta, double vb)
+{
+    return delta > vb ? 1 : (delta >= vb - 2.0 * kBand ? 2 : 0);
 }
 
 __device__ inline bool accept_full(double delta, uint64_t u53)
 {
-    int f = accept_fast(delta, log_uniform(u53));
+    const int f = decide_fast(delta, threshold_of(u53));
     return f == 2 ? accept_slow(delta, u53) : (f == 1);
 }
 
@@ -184,6 +182,7 @@ struct Inst {
     int32_t model, q, L, N, W, h, m, S, WB, log2m;
     int32_t flat_num, flat_den, kfinal, exch, wpr;
     int64_t X;
+    int64_t XP;         // row stride of the draw buffers: X rounded up to 32
     uint32_t k0, k1;
     // device arrays
     uint64_t* lat;      // Ising: [L*wpr][S] words, bit x of row y's word = spin up
@@ -199,8 +198,9 @@ struct Inst {
     int32_t* done;      // [h]
     uint8_t* flat;      // [S]   latched flatness
     int8_t* swaps;      // [S]   last interval: 1 swapped, 0 rejected, -1 none
-    uint32_t* rpack;    // [X][S] row | col << 8 | potts offset << 16
-    double* rv;         // [X][S] log(u53 2^-53)
+    uint32_t* rpack;    // [S][XP] Ising: row | col<<8 | row_up<<16 | row_down<<24;
+                        //         Potts: row | col<<8 | proposal offset<<16
+    double* rv;         // [S][XP] threshold log(u53 2^-53) + band
     int64_t* ex_prop;   // [h]
     int64_t* ex_acc;    // [h]
     int32_t* merges;    // [h] interval of each window's last merge

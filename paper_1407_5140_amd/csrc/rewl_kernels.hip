@@ -16,9 +16,13 @@
 namespace rewl {
 
 // --------------------------------------------------------------------- RNG
-// For instance i, entries e = j*S + slot, j < X.  pack = row | col<<8 | off<<16
-// where site = floor(x0 N / 2^32), row = site / L, col = site % L, and the
-// Potts proposal offset off = floor(x1 (q-1) / 2^32); v = log(u53 2^-53).
+// For instance i, walker row `slot` holds the interval's X draws contiguously
+// (row stride XP = X rounded up to the sweep's chunk pair): entry slot*XP + j
+// has site = floor(x0 N / 2^32), row = site / L, col = site % L, and
+//   Ising pack = row | col<<8 | row_up<<16 | row_down<<24 (periodic rows),
+//   Potts pack = row | col<<8 | off<<16, off = floor(x1 (q-1) / 2^32),
+// and the acceptance threshold of u53 (threshold_of).  Consecutive threads take
+// consecutive j (coalesced stores).
 __global__ void __launch_bounds__(256) k_rng(const Inst* __restrict__ insts,
                                              const int32_t* __restrict__ block_start, int n_inst)
 {
@@ -31,37 +35,44 @@ __global__ void __launch_bounds__(256) k_rng(const Inst* __restrict__ insts,
     }
     const Inst& I = insts[lo];
     if (I.ctr->all_done) return;
-    const int64_t n = I.X * I.S;
-    const int64_t nthreads = (int64_t)(block_start[lo + 1] - block_start[lo]) * blockDim.x;
-    const int64_t t = I.ctr->t;
-    const uint64_t T0 = (uint64_t)t * (uint64_t)I.X;
+    const uint32_t X = (uint32_t)I.X, XP = (uint32_t)I.XP;
+    const uint32_t n = X * (uint32_t)I.S;      // < 2^32, checked at creation
+    const uint32_t nthreads = (uint32_t)(block_start[lo + 1] - block_start[lo]) * blockDim.x;
+    const uint64_t T0 = (uint64_t)I.ctr->t * (uint64_t)X;
     const uint32_t N = I.N, L = I.L, qm1 = I.q - 1;
-    for (int64_t e = (int64_t)(b - block_start[lo]) * blockDim.x + threadIdx.x; e < n; e += nthreads) {
-        const int64_t j = e / I.S;
-        const uint32_t slot = (uint32_t)(e - j * I.S);
-        const u32x4 x = draw(I.k0, I.k1, T0 + (uint64_t)j, slot, kTagFlip);
+    for (uint32_t e = (uint32_t)(b - block_start[lo]) * blockDim.x + threadIdx.x; e < n; e += nthreads) {
+        const uint32_t slot = e / X;
+        const uint32_t j = e - slot * X;
+        const u32x4 x = draw(I.k0, I.k1, T0 + j, slot, kTagFlip);
         const uint32_t site = (uint32_t)(((uint64_t)x.x * N) >> 32);
         const uint32_t row = site / L, col = site - row * L;
-        const uint32_t off = I.model ? (uint32_t)(((uint64_t)x.y * qm1) >> 32) : 0u;
-        I.rpack[e] = row | (col << 8) | (off << 16);
-        I.rv[e] = log_uniform(u53_of(x));
+        uint32_t pack;
+        if (I.model) {
+            pack = row | (col << 8) | ((uint32_t)(((uint64_t)x.y * qm1) >> 32) << 16);
+        } else {
+            const uint32_t ru = row == 0 ? L - 1 : row - 1, rd = row == L - 1 ? 0 : row + 1;
+            pack = row | (col << 8) | (ru << 16) | (rd << 24);
+        }
+        const size_t idx = (size_t)slot * XP + j;
+        I.rpack[idx] = pack;
+        I.rv[idx] = threshold_of(u53_of(x));
     }
 }
 
 // ------------------------------------------------------------------- sweep
-struct SweepLds {
-    double* base;     // [WB]
-    uint32_t* H;      // [WB][nw]
-    uint8_t* mask;    // [WB]
-    void* lat;        // Ising [L*wpr][nw] u64, Potts [N][nw] u8
-};
-
-__device__ __forceinline__ size_t align8(size_t v) { return (v + 7) & ~size_t(7); }
+// LDS of one tile of nw walkers of window a:
+//   base [kPad + WB + kPad]         window ln g base, +inf in the pads
+//   H    [(kPad + WB + kPad) << lnw] per-walker counts, bin-major (lane minor)
+//   lat  Ising [L*wpr << lnw] u64 words / Potts [N << lnw] bytes
+// A move changes the bin by at most 2 (Ising) or 4 (Potts), so a proposal
+// outside the window lands in a pad, sees ln g = +inf and is rejected.
+constexpr int kPad = 4;
 
 __host__ __device__ inline size_t sweep_lds_bytes(int model, int L, int wpr, int WB, int nw)
 {
-    size_t s = (size_t)WB * 8 + (size_t)WB * nw * 4;
-    s = (s + WB + 7) & ~size_t(7);
+    const size_t nb = (size_t)WB + 2 * kPad;
+    size_t s = nb * 8 + nb * nw * 4;
+    s = (s + 7) & ~size_t(7);
     s += model == 0 ? (size_t)L * wpr * nw * 8 : (size_t)L * L * nw;
     return s;
 }
@@ -73,190 +84,210 @@ __device__ __noinline__ bool slow_decide(const Inst& I, uint64_t T, uint32_t slo
     return accept_slow(delta, u53_of(draw(I.k0, I.k1, T, slot, kTagFlip)));
 }
 
-// Ising, bit-packed rows (WPR words of 64 bits per row).
-template <int WPR>
-__device__ __forceinline__ int ising_aligned(const uint64_t* lat, int nw, int lane, int L, int r,
-                                             int c, int& word_idx, uint64_t& word, int& bit)
+// Native vectors for the draw chunks, loaded from the global address space
+// (plain vector loads rather than flat addressing).
+typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+typedef double v2d __attribute__((ext_vector_type(2)));
+template <class T>
+__device__ __forceinline__ T gload(const T* p)
 {
-    const int ru = r == 0 ? L - 1 : r - 1;
-    const int rd = r == L - 1 ? 0 : r + 1;
-    const int cl = c == 0 ? L - 1 : c - 1;
-    const int cr = c == L - 1 ? 0 : c + 1;
-    if (WPR == 1) {
-        word_idx = r;
-        word = lat[r * nw + lane];
-        const uint64_t wu = lat[ru * nw + lane];
-        const uint64_t wd = lat[rd * nw + lane];
-        bit = c;
-        const uint32_t s = (uint32_t)(word >> c) & 1u;
-        const uint32_t diff = ((uint32_t)(wu >> c) & 1u) + ((uint32_t)(wd >> c) & 1u) +
-                              ((uint32_t)(word >> cl) & 1u) + ((uint32_t)(word >> cr) & 1u);
-        // aligned neighbours: s=1 -> count of ones, s=0 -> count of zeros
-        return s ? (int)diff : 4 - (int)diff;
-    } else {
-        auto spin = [&](int rr, int cc) -> uint32_t {
-            return (uint32_t)(lat[(rr * WPR + (cc >> 6)) * nw + lane] >> (cc & 63)) & 1u;
-        };
-        word_idx = r * WPR + (c >> 6);
-        word = lat[word_idx * nw + lane];
-        bit = c & 63;
-        const uint32_t s = (uint32_t)(word >> bit) & 1u;
-        const uint32_t ones = spin(ru, c) + spin(rd, c) + spin(r, cl) + spin(r, cr);
-        return s ? (int)ones : 4 - (int)ones;
-    }
+    return *(const __attribute__((address_space(1))) T*)p;
 }
 
 template <int MODEL, int WPR>
 __device__ void sweep_tile(const Inst& I, const Tile& tile, char* smem)
 {
     const int a = tile.window, nw = tile.nw, lane = threadIdx.x;
-    const int WB = I.WB, L = I.L, S = I.S;
+    const int WB = I.WB, L = I.L, S = I.S, N = I.N;
     const int slot0 = a * I.m + tile.r0;
     const int lo = I.lo[a];
-    SweepLds lds;
-    lds.base = (double*)smem;
-    lds.H = (uint32_t*)(lds.base + WB);
-    lds.mask = (uint8_t*)(lds.H + (size_t)WB * nw);
-    lds.lat = (void*)(smem + align8((size_t)WB * 8 + (size_t)WB * nw * 4 + WB));
+    const int nbins = WB + 2 * kPad;
+    double* lbase = (double*)smem;                               // index kPad + bin
+    uint32_t* lH = (uint32_t*)(lbase + nbins);                   // index (kPad + bin) << lnw | lane
+    char* latp = smem + ((nbins * 8 + (size_t)nbins * nw * 4 + 7) & ~size_t(7));
     const int nthr = blockDim.x;
-    const int lnw = __builtin_ctz(nw);            // nw is a power of two
+    const int lnw = __builtin_ctz(nw);                           // nw is a power of two
 
-    // ---- stage the window table, the tile's histograms and lattices in LDS
-    for (int i = lane; i < WB; i += nthr) {
-        lds.base[i] = I.base[(size_t)a * WB + i];
-        lds.mask[i] = I.mask[lo + i];
+    // ---- stage the window table, the tile's histograms and lattices in LDS;
+    //      levels that never occur carry the sentinel 0xffffffff (never visited,
+    //      excluded from the flatness minimum, written back as 0)
+    for (int i = lane; i < nbins; i += nthr) {
+        const int b = i - kPad;
+        lbase[i] = (b >= 0 && b < WB) ? I.base[(size_t)a * WB + b] : __builtin_inf();
     }
-    for (int i = lane; i < WB * nw; i += nthr) {
-        const int b = i >> lnw, l = i & (nw - 1);
-        lds.H[i] = I.H[((size_t)a * WB + b) * I.m + tile.r0 + l];
+    for (int i = lane; i < (nbins << lnw); i += nthr) {
+        const int b = (i >> lnw) - kPad, l = i & (nw - 1);
+        uint32_t hv = 0;
+        if (b >= 0 && b < WB)
+            hv = I.mask[lo + b] ? I.H[((size_t)a * WB + b) * I.m + tile.r0 + l] : 0xffffffffu;
+        lH[i] = hv;
     }
     if (MODEL == 0) {
-        uint64_t* lat = (uint64_t*)lds.lat;
-        const int nwords = L * WPR;
-        for (int i = lane; i < nwords * nw; i += nthr) {
-            const int w = i >> lnw, l = i & (nw - 1);
-            lat[i] = I.lat[(size_t)w * S + slot0 + l];
-        }
+        uint64_t* lat = (uint64_t*)latp;
+        for (int i = lane; i < ((L * WPR) << lnw); i += nthr)
+            lat[i] = I.lat[(size_t)(i >> lnw) * S + slot0 + (i & (nw - 1))];
     } else {
-        uint8_t* lat = (uint8_t*)lds.lat;
-        for (int i = lane; i < I.N * nw; i += nthr) {
-            const int w = i >> lnw, l = i & (nw - 1);
-            lat[i] = I.plat[(size_t)w * S + slot0 + l];
-        }
+        uint8_t* lat = (uint8_t*)latp;
+        for (int i = lane; i < (N << lnw); i += nthr)
+            lat[i] = I.plat[(size_t)(i >> lnw) * S + slot0 + (i & (nw - 1))];
     }
     __syncthreads();
 
     const int k = I.k[a];
-    const bool upd = I.done[a] == 0;
+    const uint32_t inc = I.done[a] == 0 ? 1u : 0u;               // converged: frozen
     const double scale = __builtin_ldexp(1.0, -k);
     const int64_t X = I.X;
     const uint64_t T0 = (uint64_t)I.ctr->t * (uint64_t)X;
-    const int wmax = WB - 1;
 
     if (lane < nw) {
         const int slot = slot0 + lane;
-        int b = I.bin[slot] - lo;
-        uint32_t hc = lds.H[(b << lnw) + lane];
-        double bc = lds.base[b];
+        int b = I.bin[slot] - lo + kPad;                         // padded bin index
+        uint32_t hc = lH[(b << lnw) + lane];
+        double bc = lbase[b];
         double lngc = __builtin_fma((double)hc, scale, bc);
-        const uint32_t* __restrict__ rp = I.rpack + slot;
-        const double* __restrict__ rvp = I.rv + slot;
-        uint32_t pk_next = rp[0];
-        double v_next = rvp[0];
-        for (int64_t j = 0; j < X; ++j) {
-            const uint32_t pk = pk_next;
-            const double v = v_next;
-            if (j + 1 < X) {
-                pk_next = rp[(j + 1) * S];
-                v_next = rvp[(j + 1) * S];
-            }
-            const int r = pk & 0xff, c = (pk >> 8) & 0xff;
-            int nb, widx = 0, bit = 0;
-            uint64_t word = 0;
-            uint8_t newv = 0;
-            int site = 0;
+
+        // one flip attempt with the precomputed draw (pk, vb) of attempt j;
+        // lH always holds the walker's current counts, including bin b
+        auto attempt = [&](uint32_t pk, double vb, int64_t j) {
+            int nb;
+            int waddr;                                           // LDS index of the flipped word/byte
+            uint64_t wnew = 0;
+            uint8_t pnew = 0;
             if (MODEL == 0) {
-                const int al = ising_aligned<WPR>((const uint64_t*)lds.lat, nw, lane, L, r, c,
-                                                  widx, word, bit);
-                nb = b + al - 2;                      // dE = 4 al - 8, bin = (E + 2N)/4
+                const uint64_t* lat = (const uint64_t*)latp;
+                const int r = pk & 0xff, c = (pk >> 8) & 0xff;
+                const int ru = (pk >> 16) & 0xff, rd = pk >> 24;
+                if (WPR == 1) {
+                    const int cl = c == 0 ? L - 1 : c - 1, cr = c == L - 1 ? 0 : c + 1;
+                    waddr = (r << lnw) + lane;
+                    const uint64_t w = lat[waddr];
+                    const uint64_t wu = lat[(ru << lnw) + lane];
+                    const uint64_t wd = lat[(rd << lnw) + lane];
+                    const uint32_t sp = (uint32_t)(w >> c) & 1u;
+                    const uint32_t ones = ((uint32_t)(wu >> c) & 1u) + ((uint32_t)(wd >> c) & 1u) +
+                                          ((uint32_t)(w >> cl) & 1u) + ((uint32_t)(w >> cr) & 1u);
+                    // aligned neighbours al: dE = 4 al - 8, bin change al - 2
+                    nb = b + (sp ? (int)ones : 4 - (int)ones) - 2;
+                    wnew = w ^ (1ull << c);
+                } else {
+                    const int cl = c == 0 ? L - 1 : c - 1, cr = c == L - 1 ? 0 : c + 1;
+                    auto spin = [&](int rr, int cc) -> uint32_t {
+                        return (uint32_t)(lat[((rr * WPR + (cc >> 6)) << lnw) + lane] >> (cc & 63)) & 1u;
+                    };
+                    waddr = ((r * WPR + (c >> 6)) << lnw) + lane;
+                    const uint64_t w = lat[waddr];
+                    const uint32_t sp = (uint32_t)(w >> (c & 63)) & 1u;
+                    const uint32_t ones = spin(ru, c) + spin(rd, c) + spin(r, cl) + spin(r, cr);
+                    nb = b + (sp ? (int)ones : 4 - (int)ones) - 2;
+                    wnew = w ^ (1ull << (c & 63));
+                }
             } else {
-                const uint8_t* lat = (const uint8_t*)lds.lat;
-                site = r * L + c;
-                const int ru = r == 0 ? L - 1 : r - 1, rd = r == L - 1 ? 0 : r + 1;
-                const int cl = c == 0 ? L - 1 : c - 1, cr = c == L - 1 ? 0 : c + 1;
-                const int s0 = lat[(site << lnw) + lane];
-                const int n0 = lat[((ru * L + c) << lnw) + lane];
-                const int n1 = lat[((rd * L + c) << lnw) + lane];
-                const int n2 = lat[((r * L + cl) << lnw) + lane];
-                const int n3 = lat[((r * L + cr) << lnw) + lane];
+                const uint8_t* lat = (const uint8_t*)latp;
+                const int r = pk & 0xff, c = (pk >> 8) & 0xff;
+                const int site = (int)__umul24((uint32_t)r, (uint32_t)L) + c;
+                const int up = r == 0 ? site + N - L : site - L;
+                const int dn = r == L - 1 ? site - N + L : site + L;
+                const int lf = c == 0 ? site + L - 1 : site - 1;
+                const int rt = c == L - 1 ? site - L + 1 : site + 1;
+                waddr = (site << lnw) + lane;
+                const int s0 = lat[waddr];
+                const int n0 = lat[(up << lnw) + lane];
+                const int n1 = lat[(dn << lnw) + lane];
+                const int n2 = lat[(lf << lnw) + lane];
+                const int n3 = lat[(rt << lnw) + lane];
                 int nv = s0 + 1 + (int)(pk >> 16);
                 nv = nv >= I.q ? nv - I.q : nv;
-                newv = (uint8_t)nv;
+                pnew = (uint8_t)nv;
                 const int nold = (n0 == s0) + (n1 == s0) + (n2 == s0) + (n3 == s0);
                 const int nnew = (n0 == nv) + (n1 == nv) + (n2 == nv) + (n3 == nv);
-                nb = b + nold - nnew;                 // dE = n(old) - n(new), bin = E + 2N
+                nb = b + nold - nnew;                            // dE = n(old) - n(new)
             }
-            const bool inwin = (unsigned)nb <= (unsigned)wmax;
-            const int nbc = inwin ? nb : b;
-            const double bn = lds.base[nbc];
-            uint32_t hn = lds.H[(nbc << lnw) + lane];
-            hn = nbc == b ? hc : hn;
-            const double lngn = __builtin_fma((double)hn, scale, bn);
-            const double delta = lngc - lngn;         // exact
-            int f = inwin ? accept_fast(delta, v) : 0;
-            if (__any(f == 2)) {
+            const double bn = lbase[nb];
+            const uint32_t hn = lH[(nb << lnw) + lane];
+            const double lngn = __builtin_fma((double)hn, scale, bn);   // +inf in a pad
+            const double delta = lngc - lngn;                    // exact (or -inf)
+            int f = decide_fast(delta, vb);
+            if (__builtin_expect(__any(f == 2), 0)) {
                 if (f == 2) f = slow_decide(I, T0 + (uint64_t)j, (uint32_t)slot, delta) ? 1 : 0;
             }
             if (f) {
-                if (nb != b) {
-                    lds.H[(b << lnw) + lane] = hc;
-                    hc = hn;
-                    bc = bn;
-                    b = nb;
-                }
-                if (MODEL == 0)
-                    ((uint64_t*)lds.lat)[(widx << lnw) + lane] = word ^ (1ull << bit);
-                else
-                    ((uint8_t*)lds.lat)[(site << lnw) + lane] = newv;
+                if (MODEL == 0) ((uint64_t*)latp)[waddr] = wnew;
+                else ((uint8_t*)latp)[waddr] = pnew;
             }
-            hc += upd ? 1u : 0u;
+            b = f ? nb : b;
+            hc = (f ? hn : hc) + inc;
+            bc = f ? bn : bc;
+            lH[(b << lnw) + lane] = hc;
             lngc = __builtin_fma((double)hc, scale, bc);
+        };
+
+        // the walker's draws arrive in register chunks of kChunk attempts; the
+        // next chunk's vector loads are in flight while this one is walked
+        constexpr int kChunk = 16;
+        const v4u* pkp = (const v4u*)(I.rpack + (size_t)slot * I.XP);
+        const v2d* vp = (const v2d*)(I.rv + (size_t)slot * I.XP);
+        v4u PA[kChunk / 4], PB[kChunk / 4];
+        v2d VA[kChunk / 2], VB[kChunk / 2];
+        auto load = [&](v4u* P, v2d* V, int64_t j0) {
+#pragma unroll
+            for (int i = 0; i < kChunk / 4; ++i) P[i] = gload(pkp + j0 / 4 + i);
+#pragma unroll
+            for (int i = 0; i < kChunk / 2; ++i) V[i] = gload(vp + j0 / 2 + i);
+        };
+        auto walk = [&](const v4u* P, const v2d* V, int64_t j0, bool check) {
+#pragma unroll
+            for (int i = 0; i < kChunk; ++i) {
+                if (!check || j0 + i < X) {
+                    const v4u q4 = P[i / 4];
+                    const uint32_t pk = (i & 3) == 0 ? q4.x : (i & 3) == 1 ? q4.y : (i & 3) == 2 ? q4.z : q4.w;
+                    const double vb = (i & 1) ? V[i / 2].y : V[i / 2].x;
+                    attempt(pk, vb, j0 + i);
+                }
+            }
+        };
+        // XP is a multiple of 2 kChunk, so every chunk load below stays inside the row
+        load(PA, VA, 0);
+        for (int64_t j0 = 0; j0 < X; j0 += 2 * kChunk) {
+            load(PB, VB, j0 + kChunk);
+            if (j0 + 2 * kChunk <= X) {
+                walk(PA, VA, j0, false);
+                if (j0 + 2 * kChunk < X) load(PA, VA, j0 + 2 * kChunk);
+                walk(PB, VB, j0 + kChunk, false);
+            } else {
+                walk(PA, VA, j0, true);
+                walk(PB, VB, j0 + kChunk, true);
+            }
         }
-        lds.H[(b << lnw) + lane] = hc;
-        I.bin[slot] = b + lo;
+        I.bin[slot] = b - kPad + lo;
         I.swaps[slot] = -1;
     }
     __syncthreads();
 
     // ---- write back
-    for (int i = lane; i < WB * nw; i += nthr) {
+    for (int i = lane; i < (WB << lnw); i += nthr) {
         const int bb = i >> lnw, l = i & (nw - 1);
-        I.H[((size_t)a * WB + bb) * I.m + tile.r0 + l] = lds.H[i];
+        const uint32_t hv = lH[((bb + kPad) << lnw) + l];
+        I.H[((size_t)a * WB + bb) * I.m + tile.r0 + l] = hv == 0xffffffffu ? 0u : hv;
     }
     if (MODEL == 0) {
-        const uint64_t* lat = (const uint64_t*)lds.lat;
-        for (int i = lane; i < L * WPR * nw; i += nthr) {
-            const int w = i >> lnw, l = i & (nw - 1);
-            I.lat[(size_t)w * S + slot0 + l] = lat[i];
-        }
+        const uint64_t* lat = (const uint64_t*)latp;
+        for (int i = lane; i < ((L * WPR) << lnw); i += nthr)
+            I.lat[(size_t)(i >> lnw) * S + slot0 + (i & (nw - 1))] = lat[i];
     } else {
-        const uint8_t* lat = (const uint8_t*)lds.lat;
-        for (int i = lane; i < I.N * nw; i += nthr) {
-            const int w = i >> lnw, l = i & (nw - 1);
-            I.plat[(size_t)w * S + slot0 + l] = lat[i];
-        }
+        const uint8_t* lat = (const uint8_t*)latp;
+        for (int i = lane; i < (N << lnw); i += nthr)
+            I.plat[(size_t)(i >> lnw) * S + slot0 + (i & (nw - 1))] = lat[i];
     }
 
     // ---- flatness of each walker (Sec. II.A): min H >= num/den * mean H over
     //      the levels of the window that occur; latched until the window merges
-    if (upd && lane < nw) {
+    if (inc && lane < nw) {
         uint32_t mn = 0xffffffffu;
         uint64_t sum = 0;
-        for (int bb = 0; bb < WB; ++bb) {
-            if (!lds.mask[bb]) continue;
-            const uint32_t v = lds.H[(bb << lnw) + lane];
-            mn = v < mn ? v : mn;
-            sum += v;
+        for (int bb = kPad; bb < WB + kPad; ++bb) {
+            const uint32_t v = lH[(bb << lnw) + lane];
+            mn = v < mn ? v : mn;                                // the sentinel never wins the min
+            sum += v == 0xffffffffu ? 0u : v;
         }
         const int slot = slot0 + lane;
         const int64_t n = I.nreach[a];
@@ -640,7 +671,7 @@ __global__ void k_accept_probe(const double* __restrict__ delta, const uint64_t*
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) {
-        const int f = accept_fast(delta[i], log_uniform(u53[i]));
+        const int f = decide_fast(delta[i], threshold_of(u53[i]));
         out[i] = f == 2 ? (accept_slow(delta[i], u53[i]) ? 3 : 2) : f;
     }
 }
