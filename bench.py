@@ -79,6 +79,8 @@ def main(argv=None):
     ap.add_argument("--workload", default="ising64", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sweep", default="auto", choices=["auto", "lane", "wave"])
+    ap.add_argument("--wpb", type=int, default=0, help="walkers per block (0 = library choice)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is "
@@ -93,10 +95,11 @@ def main(argv=None):
     S = kw["n_windows"] * kw["m"]
     X = kw["X"]
     t_create = time.perf_counter()
-    g = rw.Rewl([cfg])
+    tune = rw.rewl_tune(args.wpb, 0, 1 << 20, {"auto": 0, "lane": 1, "wave": 2}[args.sweep])
+    g = rw.Rewl([cfg], tune=tune)
     t_create = time.perf_counter() - t_create
     info = g.info()
-    print(f"[bench] {label}: {S} walkers, walkers/block {info['walkers_per_block']}, "
+    print(f"[bench] {label}: {S} walkers, {info['sweep_kind']} sweep, walkers/block {info['walkers_per_block']}, "
           f"LDS {info['lds_bytes']} B, create {t_create:.2f} s", file=sys.stderr, flush=True)
 
     rw.rewl_run_exact(g.h, args.warmup)
@@ -133,10 +136,11 @@ def main(argv=None):
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": label, "walkers": S, "attempts_per_step": S * X,
-                   "walkers_per_block": info["walkers_per_block"]},
+                   "sweep": info["sweep_kind"], "walkers_per_block": info["walkers_per_block"]},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
                      "unit": "Tops/s", "frac": achieved / PEAK_LANE_OPS, "traffic": None,
-                     "kernel": "k_sweep", "kernel_ms": sweep_ms,
+                     "kernel": "k_sweep_wave" if info["sweep_kind"] == "wave" else "k_sweep",
+                     "kernel_ms": sweep_ms,
                      "ops_per_attempt": OPS_PER_ATTEMPT[kw["model"]]},
         "sweep_attempts_per_s": S * X / (sweep_ms * 1e-3),
     }

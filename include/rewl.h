@@ -58,12 +58,19 @@ typedef struct {
     uint64_t seed;              /* Philox4x32-10 key                                     */
 } rewl_config;
 
+/* Sweep variants.  LANE: one walker per lane, draws precomputed for the whole
+ * interval by a separate kernel (suits batches of many thousands of walkers).
+ * WAVE: one walker per wave, the chain on wave-uniform values, the lanes draw
+ * the next 64 attempts (suits few walkers; Ising needs L <= 64).               */
+enum { REWL_SWEEP_AUTO = 0, REWL_SWEEP_LANE = 1, REWL_SWEEP_WAVE = 2 };
+
 /* Optional tuning of a batch (NULL = library choice). */
 typedef struct {
-    int32_t walkers_per_block;  /* walkers staged per LDS tile (power of two <= 64), 0 = auto */
+    int32_t walkers_per_block;  /* LANE: walkers per LDS tile (power of two <= 64);
+                                   WAVE: walkers (waves) per block (<= 8); 0 = auto   */
     int32_t use_graph;          /* 1: replay the interval as a captured HIP graph        */
     int32_t poll_every;         /* intervals between host checks of the done flags      */
-    int32_t reserved;
+    int32_t sweep_kind;         /* REWL_SWEEP_*, applied to every instance that allows it */
 } rewl_tune;
 
 typedef struct rewl_handle rewl_handle;
@@ -148,8 +155,9 @@ rewl_status rewl_restore(rewl_handle* h, const void* buf, size_t len);
 void rewl_destroy(rewl_handle* h);
 const char* rewl_last_error(void);
 
-/* Number of instances and the chosen walkers-per-block of one instance. */
-rewl_status rewl_info(rewl_handle* h, int32_t instance, int32_t* n_instances,
+/* Number of instances, and for one instance the sweep variant chosen
+ * (REWL_SWEEP_LANE / _WAVE), walkers per block and LDS bytes per block.       */
+rewl_status rewl_info(rewl_handle* h, int32_t instance, int32_t* n_instances, int32_t* sweep_kind,
                       int32_t* walkers_per_block, size_t* lds_bytes);
 
 /* Diagnostics (run on the device, used by the tests):

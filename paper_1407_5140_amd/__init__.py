@@ -43,9 +43,12 @@ class rewl_config(ctypes.Structure):
                 ("seed", ctypes.c_uint64)]
 
 
+REWL_SWEEP_AUTO, REWL_SWEEP_LANE, REWL_SWEEP_WAVE = 0, 1, 2
+
+
 class rewl_tune(ctypes.Structure):
     _fields_ = [("walkers_per_block", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-                ("poll_every", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("poll_every", ctypes.c_int32), ("sweep_kind", ctypes.c_int32)]
 
 
 class rewl_stats(ctypes.Structure):
@@ -73,7 +76,7 @@ _sigs = {
     "rewl_checkpoint": ([_vp, _vp, _P(ctypes.c_size_t)], ctypes.c_int),
     "rewl_restore": ([_vp, _vp, ctypes.c_size_t], ctypes.c_int),
     "rewl_destroy": ([_vp], None),
-    "rewl_info": ([_vp, ctypes.c_int32, _vp, _vp, _vp], ctypes.c_int),
+    "rewl_info": ([_vp, ctypes.c_int32, _vp, _vp, _vp, _vp], ctypes.c_int),
     "rewl_probe_accept": ([_vp, _vp, ctypes.c_int32, _vp], ctypes.c_int),
     "rewl_probe_philox": ([_vp, ctypes.c_int32, _vp], ctypes.c_int),
 }
@@ -208,10 +211,11 @@ def rewl_destroy(h) -> None:
 
 
 def rewl_info(h, instance: int = 0) -> dict:
-    n, w, lds = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_size_t()
-    _check(_lib.rewl_info(h, instance, ctypes.byref(n), ctypes.byref(w), ctypes.byref(lds)),
-           "rewl_info")
-    return dict(n_instances=n.value, walkers_per_block=w.value, lds_bytes=lds.value)
+    n, kind, w, lds = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_size_t()
+    _check(_lib.rewl_info(h, instance, ctypes.byref(n), ctypes.byref(kind), ctypes.byref(w),
+                          ctypes.byref(lds)), "rewl_info")
+    return dict(n_instances=n.value, sweep_kind={1: "lane", 2: "wave"}[kind.value],
+                walkers_per_block=w.value, lds_bytes=lds.value)
 
 
 def rewl_probe_accept(delta, u53) -> np.ndarray:

@@ -120,7 +120,7 @@ rewl_status validate(const rewl_config& c)
 
 struct HostInst {
     rewl_config cfg;
-    int N, W, h, m, S, WB, log2m, wpr, wpb;
+    int N, W, h, m, S, WB, log2m, wpr, wpb, kind;
     size_t lds;
     std::vector<int32_t> lo, hi, nreach;
     std::vector<uint8_t> mask;
@@ -138,6 +138,10 @@ struct rewl_handle {
     Inst* d_insts = nullptr;
     Tile* d_tiles = nullptr;
     int ntiles = 0;
+    Tile* d_wtiles = nullptr;
+    int nwtiles = 0;
+    int wave_threads = 64;
+    size_t max_lds_wave = 0;
     int2* d_merge = nullptr;
     int nmerge = 0;
     int32_t* d_rng_start = nullptr;
@@ -174,11 +178,16 @@ namespace {
 rewl_status enqueue_interval(rewl_handle* H, bool time_it)
 {
     if (time_it) HIP_TRY(hipEventRecord(H->ev[0], H->stream));
-    hipLaunchKernelGGL(k_rng, dim3(H->rng_grid), dim3(256), 0, H->stream, H->d_insts,
-                       H->d_rng_start, H->n);
+    if (H->rng_grid > 0)
+        hipLaunchKernelGGL(k_rng, dim3(H->rng_grid), dim3(256), 0, H->stream, H->d_insts,
+                           H->d_rng_start, H->n);
     if (time_it) HIP_TRY(hipEventRecord(H->ev[1], H->stream));
-    hipLaunchKernelGGL(k_sweep, dim3(H->ntiles), dim3(64), H->max_lds, H->stream, H->d_insts,
-                       H->d_tiles, H->ntiles);
+    if (H->ntiles > 0)
+        hipLaunchKernelGGL(k_sweep, dim3(H->ntiles), dim3(64), H->max_lds, H->stream, H->d_insts,
+                           H->d_tiles, H->ntiles);
+    if (H->nwtiles > 0)
+        hipLaunchKernelGGL(k_sweep_wave, dim3(H->nwtiles), dim3(H->wave_threads), H->max_lds_wave,
+                           H->stream, H->d_insts, H->d_wtiles, H->nwtiles);
     if (time_it) HIP_TRY(hipEventRecord(H->ev[2], H->stream));
     hipLaunchKernelGGL(k_merge, dim3(H->nmerge), dim3(256), 0, H->stream, H->d_insts, H->d_merge);
     if (H->exch_threads > 0)
@@ -337,7 +346,7 @@ static rewl_status create_impl(const rewl_config* cfgs, int32_t n, void* hip_str
     H->n = n;
     H->inst.resize(n);
     std::vector<Inst> devs(n);
-    std::vector<Tile> tiles;
+    std::vector<Tile> tiles, wtiles;
     std::vector<int2> merges;
     std::vector<int32_t> rng_start(1, 0), exch_start(1, 0), slot_start(1, 0);
     auto bail = [&](rewl_status s) {
@@ -371,15 +380,38 @@ static rewl_status create_impl(const rewl_config* cfgs, int32_t n, void* hip_str
         hi.nreach.assign(hi.h, 0);
         for (int a = 0; a < hi.h; ++a)
             for (int b = hi.lo[a]; b <= hi.hi[a]; ++b) hi.nreach[a] += hi.mask[b];
-        int want = H->tune.walkers_per_block > 0 ? H->tune.walkers_per_block : 64;
-        int wpb = 1;
-        while (wpb * 2 <= std::min(want, std::min(64, hi.m))) wpb *= 2;
-        while (wpb > 1 && sweep_lds_bytes(c.model, c.L, hi.wpr, hi.WB, wpb) > (size_t)lds_limit) wpb /= 2;
-        hi.wpb = wpb;
-        hi.lds = sweep_lds_bytes(c.model, c.L, hi.wpr, hi.WB, wpb);
+        // sweep variant.  Both issue ~70 instructions per attempt step; the lane
+        // variant serves a whole wave of walkers with them, the wave variant one.
+        // With few walkers the chain latency, not the GPU's width, sets the rate
+        // and the two are on par for Ising (measured); the lane variant is chosen
+        // otherwise.
+        const bool wave_ok = c.model == 1 || c.L <= 64;
+        int64_t total_walkers = 0;
+        for (int u = 0; u < n; ++u) total_walkers += (int64_t)cfgs[u].n_windows * cfgs[u].walkers_per_window;
+        hi.kind = REWL_SWEEP_LANE;
+        if (wave_ok && (H->tune.sweep_kind == REWL_SWEEP_WAVE ||
+                        (H->tune.sweep_kind == REWL_SWEEP_AUTO && c.model == 0 && total_walkers <= 2048)))
+            hi.kind = REWL_SWEEP_WAVE;
+        if (hi.kind == REWL_SWEEP_LANE) {
+            int want = H->tune.walkers_per_block > 0 ? H->tune.walkers_per_block : 64;
+            int wpb = 1;
+            while (wpb * 2 <= std::min(want, std::min(64, hi.m))) wpb *= 2;
+            while (wpb > 1 && sweep_lds_bytes(c.model, c.L, hi.wpr, hi.WB, wpb) > (size_t)lds_limit) wpb /= 2;
+            hi.wpb = wpb;
+            hi.lds = sweep_lds_bytes(c.model, c.L, hi.wpr, hi.WB, wpb);
+            H->max_lds = std::max(H->max_lds, hi.lds);
+        } else {
+            int want = H->tune.walkers_per_block > 0 ? H->tune.walkers_per_block : 4;
+            int G = 1;
+            while (G * 2 <= std::min(want, std::min(8, hi.m))) G *= 2;
+            while (G > 1 && wave_lds_bytes(c.model, c.L, hi.WB, G) > (size_t)lds_limit) G /= 2;
+            hi.wpb = G;
+            hi.lds = wave_lds_bytes(c.model, c.L, hi.WB, G);
+            H->max_lds_wave = std::max(H->max_lds_wave, hi.lds);
+            H->wave_threads = std::max(H->wave_threads, 64 * G);
+        }
         if (hi.lds > (size_t)lds_limit)
             return bail(fail(REWL_E_INVALID, "instance " + std::to_string(i) + ": one walker's tables exceed LDS"));
-        H->max_lds = std::max(H->max_lds, hi.lds);
 
         Inst& d = hi.dev;
         std::memset(&d, 0, sizeof(d));
@@ -405,8 +437,9 @@ static rewl_status create_impl(const rewl_config* cfgs, int32_t n, void* hip_str
         if (s == REWL_OK) s = H->alloc(&d.done, h);
         if (s == REWL_OK) s = H->alloc(&d.flat, S);
         if (s == REWL_OK) s = H->alloc(&d.swaps, S);
-        if (s == REWL_OK) s = H->alloc(&d.rpack, (size_t)d.XP * S);
-        if (s == REWL_OK) s = H->alloc(&d.rv, (size_t)d.XP * S);
+        const size_t ndraw = hi.kind == REWL_SWEEP_LANE ? (size_t)d.XP * S : 1;
+        if (s == REWL_OK) s = H->alloc(&d.rpack, ndraw);
+        if (s == REWL_OK) s = H->alloc(&d.rv, ndraw);
         if (s == REWL_OK) s = H->alloc(&d.ex_prop, h);
         if (s == REWL_OK) s = H->alloc(&d.ex_acc, h);
         if (s == REWL_OK) s = H->alloc(&d.merges, h);
@@ -434,10 +467,13 @@ static rewl_status create_impl(const rewl_config* cfgs, int32_t n, void* hip_str
 
         for (int a = 0; a < hi.h; ++a) {
             merges.push_back(make_int2(i, a));
-            for (int r0 = 0; r0 < hi.m; r0 += wpb) tiles.push_back({i, a, r0, wpb});
+            for (int r0 = 0; r0 < hi.m; r0 += hi.wpb)
+                (hi.kind == REWL_SWEEP_LANE ? tiles : wtiles).push_back({i, a, r0, hi.wpb});
         }
         const int64_t work = c.exchange_interval * (int64_t)S;
-        const int64_t nb = std::min<int64_t>(std::max<int64_t>((work + 2047) / 2048, 1), 16384);
+        const int64_t nb = hi.kind != REWL_SWEEP_LANE
+                               ? 0
+                               : std::min<int64_t>(std::max<int64_t>((work + 2047) / 2048, 1), 16384);
         rng_start.push_back(rng_start.back() + (int32_t)nb);
         exch_start.push_back(exch_start.back() + ((c.exchange_enabled && hi.h > 1) ? (hi.h - 1) * hi.m : 0));
         slot_start.push_back(slot_start.back() + hi.S);
@@ -453,12 +489,14 @@ static rewl_status create_impl(const rewl_config* cfgs, int32_t n, void* hip_str
         devs[i] = H->inst[i].dev;
     }
     H->ntiles = (int)tiles.size();
+    H->nwtiles = (int)wtiles.size();
     H->nmerge = (int)merges.size();
     H->rng_grid = rng_start.back();
     H->exch_threads = exch_start.back();
     H->slot_threads = slot_start.back();
     if ((s = H->alloc(&H->d_insts, n)) != REWL_OK) return bail(s);
     if ((s = H->alloc(&H->d_tiles, tiles.size())) != REWL_OK) return bail(s);
+    if ((s = H->alloc(&H->d_wtiles, wtiles.size())) != REWL_OK) return bail(s);
     if ((s = H->alloc(&H->d_merge, merges.size())) != REWL_OK) return bail(s);
     if ((s = H->alloc(&H->d_rng_start, rng_start.size())) != REWL_OK) return bail(s);
     if ((s = H->alloc(&H->d_exch_start, exch_start.size())) != REWL_OK) return bail(s);
@@ -466,7 +504,10 @@ static rewl_status create_impl(const rewl_config* cfgs, int32_t n, void* hip_str
     bool ok = true;
     hipStream_t st = H->stream;
     ok &= hipMemcpyAsync(H->d_insts, devs.data(), sizeof(Inst) * n, hipMemcpyHostToDevice, st) == hipSuccess;
-    ok &= hipMemcpyAsync(H->d_tiles, tiles.data(), sizeof(Tile) * tiles.size(), hipMemcpyHostToDevice, st) == hipSuccess;
+    if (!tiles.empty())
+        ok &= hipMemcpyAsync(H->d_tiles, tiles.data(), sizeof(Tile) * tiles.size(), hipMemcpyHostToDevice, st) == hipSuccess;
+    if (!wtiles.empty())
+        ok &= hipMemcpyAsync(H->d_wtiles, wtiles.data(), sizeof(Tile) * wtiles.size(), hipMemcpyHostToDevice, st) == hipSuccess;
     ok &= hipMemcpyAsync(H->d_merge, merges.data(), sizeof(int2) * merges.size(), hipMemcpyHostToDevice, st) == hipSuccess;
     ok &= hipMemcpyAsync(H->d_rng_start, rng_start.data(), 4 * rng_start.size(), hipMemcpyHostToDevice, st) == hipSuccess;
     ok &= hipMemcpyAsync(H->d_exch_start, exch_start.data(), 4 * exch_start.size(), hipMemcpyHostToDevice, st) == hipSuccess;
@@ -474,7 +515,9 @@ static rewl_status create_impl(const rewl_config* cfgs, int32_t n, void* hip_str
     ok &= hipStreamSynchronize(st) == hipSuccess;
     if (!ok) return bail(fail(REWL_E_DEVICE, "descriptor upload failed"));
     if (hipFuncSetAttribute((const void*)k_sweep, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)H->max_lds) != hipSuccess)
+                            (int)std::max<size_t>(H->max_lds, 1)) != hipSuccess ||
+        hipFuncSetAttribute((const void*)k_sweep_wave, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)std::max<size_t>(H->max_lds_wave, 1)) != hipSuccess)
         return bail(fail(REWL_E_DEVICE, "cannot raise the dynamic LDS limit"));
 
     hipLaunchKernelGGL(k_init, dim3((H->slot_threads + 127) / 128), dim3(128), 0, st, H->d_insts,
@@ -554,11 +597,13 @@ rewl_status rewl_set_timing(rewl_handle* H, int32_t on)
     return REWL_OK;
 }
 
-rewl_status rewl_info(rewl_handle* H, int32_t i, int32_t* n_instances, int32_t* wpb, size_t* lds)
+rewl_status rewl_info(rewl_handle* H, int32_t i, int32_t* n_instances, int32_t* kind, int32_t* wpb,
+                      size_t* lds)
 {
     rewl_status s = check_inst(H, i);
     if (s != REWL_OK) return s;
     if (n_instances) *n_instances = H->n;
+    if (kind) *kind = H->inst[i].kind;
     if (wpb) *wpb = H->inst[i].wpb;
     if (lds) *lds = H->inst[i].lds;
     return REWL_OK;

@@ -312,6 +312,226 @@ __global__ void __launch_bounds__(64) k_sweep(const Inst* __restrict__ insts,
     }
 }
 
+// -------------------------------------------------------------- wave sweep
+// One wave per walker, for workloads with few walkers: the walker's Markov
+// chain runs on wave-uniform (scalar) values, and the 64 lanes draw the Philox
+// numbers of the next 64 attempts in parallel (no draw buffer).
+//   Ising (L <= 64): lane y holds lattice row y; rows are read with v_readlane.
+//   Potts: the walker's lattice is one byte per site in LDS (uniform addresses).
+// LDS: base [nbins] shared by the block's walkers (all of one window), then per
+// wave its counts H [nbins], then (Potts) per wave its lattice [N].
+__host__ __device__ inline size_t wave_lds_bytes(int model, int L, int WB, int G)
+{
+    const size_t nb = (size_t)WB + 2 * kPad;
+    size_t s = nb * 8 + (size_t)G * nb * 4;
+    s = (s + 7) & ~size_t(7);
+    if (model == 1) s += (size_t)G * L * L;
+    return s;
+}
+
+__device__ __forceinline__ uint32_t rl(uint32_t v, int l)
+{
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
+}
+__device__ __forceinline__ uint64_t rl64(uint64_t v, int l)
+{
+    return ((uint64_t)rl((uint32_t)(v >> 32), l) << 32) | rl((uint32_t)v, l);
+}
+__device__ __forceinline__ double rld(double v, int l)
+{
+    return __builtin_bit_cast(double, rl64(__builtin_bit_cast(uint64_t, v), l));
+}
+
+template <int MODEL>
+__device__ void sweep_wave(const Inst& I, const Tile& tile, char* smem)
+{
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int G = tile.nw;
+    const int a = tile.window, WB = I.WB, L = I.L, S = I.S, N = I.N;
+    const int nbins = WB + 2 * kPad;
+    const int lo = I.lo[a];
+    double* lbase = (double*)smem;
+    for (int i = threadIdx.x; i < nbins; i += blockDim.x) {
+        const int b = i - kPad;
+        lbase[i] = (b >= 0 && b < WB) ? I.base[(size_t)a * WB + b] : __builtin_inf();
+    }
+    const bool active = wave < G;
+    const int r = tile.r0 + wave, slot = a * I.m + r;
+    uint32_t* lH = (uint32_t*)(lbase + nbins) + (size_t)wave * nbins;
+    uint8_t* llat = (uint8_t*)(smem + ((nbins * 8 + (size_t)G * nbins * 4 + 7) & ~size_t(7))) +
+                    (size_t)wave * N;
+    uint64_t row = 0;
+    if (active) {
+        for (int i = lane; i < nbins; i += 64) {
+            const int b = i - kPad;
+            uint32_t hv = 0;
+            if (b >= 0 && b < WB)
+                hv = I.mask[lo + b] ? I.H[((size_t)a * WB + b) * I.m + r] : 0xffffffffu;
+            lH[i] = hv;
+        }
+        if (MODEL == 0) {
+            if (lane < L) row = I.lat[(size_t)lane * S + slot];
+        } else {
+            for (int i = lane; i < N; i += 64) llat[i] = I.plat[(size_t)i * S + slot];
+        }
+    }
+    __syncthreads();
+    if (!active) return;
+
+    const int k = I.k[a];
+    const uint32_t inc = I.done[a] == 0 ? 1u : 0u;
+    const double scale = __builtin_ldexp(1.0, -k);
+    const int64_t X = I.X;
+    const uint64_t T0 = (uint64_t)I.ctr->t * (uint64_t)X;
+    const uint32_t q = (uint32_t)I.q, qm1 = q - 1;
+    int b = __builtin_amdgcn_readfirstlane(I.bin[slot] - lo + kPad);
+    // ln g of the walker's current state, kept incrementally: every step adds
+    // 2^-k (exact), a move replaces it by the candidate's value
+    double lngc = __builtin_fma((double)lH[b], scale, lbase[b]);
+    const double incv = inc ? scale : 0.0;
+    // lane l (l <= 8) evaluates candidate bin b + l - 4 of every attempt
+    const int cand = (lane < 8 ? lane : 8) - 4;
+    uint32_t rlo = (uint32_t)row, rhi = (uint32_t)(row >> 32);
+
+    for (int64_t j0 = 0; j0 < X; j0 += 64) {
+        // lane l draws attempt j0 + l
+        const u32x4 x = draw(I.k0, I.k1, T0 + (uint64_t)(j0 + lane), (uint32_t)slot, kTagFlip);
+        const uint32_t site = (uint32_t)(((uint64_t)x.x * (uint32_t)N) >> 32);
+        const uint32_t rr = site / (uint32_t)L, cc = site - rr * (uint32_t)L;
+        uint32_t p0;
+        if (MODEL == 0) {
+            const uint32_t ru = rr == 0 ? L - 1 : rr - 1, rd = rr == (uint32_t)L - 1 ? 0 : rr + 1;
+            p0 = rr | (ru << 8) | (rd << 16) | (cc << 24);
+        } else {
+            p0 = rr | (cc << 8) | ((uint32_t)(((uint64_t)x.y * qm1) >> 32) << 16);
+        }
+        const double vbl = threshold_of(u53_of(x));
+        const int n = (int)((X - j0) < 64 ? (X - j0) : 64);
+        for (int i = 0; i < n; ++i) {
+            const uint32_t pk = rl(p0, i);
+            const double vb = rld(vbl, i);
+            // candidate outcomes, all lanes at once (pads give +inf -> reject)
+            const int nbl = b + cand;
+            const double lngn = __builtin_fma((double)lH[nbl], scale, lbase[nbl]);
+            const double dl = lngc - lngn;
+            // the move itself (wave-uniform): bin change d
+            int d, wsite = 0, rrow = 0;
+            uint32_t pnew = 0, nlo = 0, nhi = 0;
+            if (MODEL == 0) {
+                rrow = pk & 0xff;
+                const int ru = (pk >> 8) & 0xff, rd = (pk >> 16) & 0xff, col = pk >> 24;
+                const int cl = col == 0 ? L - 1 : col - 1, cr = col == L - 1 ? 0 : col + 1;
+                const uint64_t w = ((uint64_t)rl(rhi, rrow) << 32) | rl(rlo, rrow);
+                const uint64_t wu = ((uint64_t)rl(rhi, ru) << 32) | rl(rlo, ru);
+                const uint64_t wd = ((uint64_t)rl(rhi, rd) << 32) | rl(rlo, rd);
+                const uint32_t sp = (uint32_t)(w >> col) & 1u;
+                const uint32_t ones = ((uint32_t)(wu >> col) & 1u) + ((uint32_t)(wd >> col) & 1u) +
+                                      ((uint32_t)(w >> cl) & 1u) + ((uint32_t)(w >> cr) & 1u);
+                d = (sp ? (int)ones : 4 - (int)ones) - 2;
+                const uint64_t wn = w ^ (1ull << col);
+                nlo = (uint32_t)wn;
+                nhi = (uint32_t)(wn >> 32);
+            } else {
+                const int r0 = pk & 0xff, c0 = (pk >> 8) & 0xff;
+                wsite = r0 * L + c0;
+                const int up = r0 == 0 ? wsite + N - L : wsite - L;
+                const int dn = r0 == L - 1 ? wsite - N + L : wsite + L;
+                const int lf = c0 == 0 ? wsite + L - 1 : wsite - 1;
+                const int rt = c0 == L - 1 ? wsite - L + 1 : wsite + 1;
+                const int s0 = llat[wsite];
+                const int n0 = llat[up], n1 = llat[dn], n2 = llat[lf], n3 = llat[rt];
+                uint32_t nv = (uint32_t)s0 + 1u + (pk >> 16);
+                nv = nv >= q ? nv - q : nv;
+                pnew = nv;
+                const int nold = (n0 == s0) + (n1 == s0) + (n2 == s0) + (n3 == s0);
+                const int nnew = (n0 == (int)nv) + (n1 == (int)nv) + (n2 == (int)nv) + (n3 == (int)nv);
+                d = __builtin_amdgcn_readfirstlane(nold - nnew);
+                pnew = (uint32_t)__builtin_amdgcn_readfirstlane((int)pnew);
+            }
+            // fast decisions of all candidates as lane masks; pick candidate d.
+            // dl - vb > 0 <=> dl > vb exactly (IEEE subtraction keeps the sign)
+            const double e = dl - vb;
+            const uint64_t acc = __ballot(e > 0.0);
+            const uint64_t und = __ballot(e >= -2.0 * kBand) & ~acc;
+            int f = (int)((acc >> (d + 4)) & 1u);
+            if (__builtin_expect((und >> (d + 4)) & 1u, 0)) {
+                const double delta = rld(dl, d + 4);
+                f = __builtin_amdgcn_readfirstlane(
+                    slow_decide(I, T0 + (uint64_t)(j0 + i), (uint32_t)slot, delta) ? 1 : 0);
+            }
+            if (f) {
+                lngc = rld(lngn, d + 4);
+                b += d;
+                if (MODEL == 0) {
+                    if (lane == rrow) {
+                        rlo = nlo;
+                        rhi = nhi;
+                    }
+                } else {
+                    if (lane == 0) llat[wsite] = (uint8_t)pnew;
+                }
+            }
+            lngc += incv;
+            if (lane == 0) atomicAdd(&lH[b], inc);          // LDS add, no return value
+        }
+    }
+    row = ((uint64_t)rhi << 32) | rlo;
+
+    // ---- write back
+    for (int i = lane; i < WB; i += 64) {
+        const uint32_t hv = lH[i + kPad];
+        I.H[((size_t)a * WB + i) * I.m + r] = hv == 0xffffffffu ? 0u : hv;
+    }
+    if (MODEL == 0) {
+        if (lane < L) I.lat[(size_t)lane * S + slot] = row;
+    } else {
+        for (int i = lane; i < N; i += 64) I.plat[(size_t)i * S + slot] = llat[i];
+    }
+    if (lane == 0) {
+        I.bin[slot] = b - kPad + lo;
+        I.swaps[slot] = -1;
+    }
+    // ---- flatness (Sec. II.A): wave-wide min and sum of the walker's counts
+    if (inc) {
+        uint32_t mn = 0xffffffffu, slo = 0, shi = 0;
+        uint64_t sum = 0;
+        for (int i = lane + kPad; i < WB + kPad; i += 64) {
+            const uint32_t v = lH[i];
+            mn = v < mn ? v : mn;
+            sum += v == 0xffffffffu ? 0u : v;
+        }
+        slo = (uint32_t)sum;
+        shi = (uint32_t)(sum >> 32);
+        for (int off = 32; off > 0; off >>= 1) {
+            const uint32_t m2 = (uint32_t)__shfl_xor((int)mn, off);
+            const uint32_t l2 = (uint32_t)__shfl_xor((int)slo, off);
+            const uint32_t h2 = (uint32_t)__shfl_xor((int)shi, off);
+            mn = m2 < mn ? m2 : mn;
+            const uint64_t s2 = (((uint64_t)shi << 32) | slo) + (((uint64_t)h2 << 32) | l2);
+            slo = (uint32_t)s2;
+            shi = (uint32_t)(s2 >> 32);
+        }
+        if (lane == 0) {
+            const uint64_t tot = ((uint64_t)shi << 32) | slo;
+            const int64_t nreach = I.nreach[a];
+            if ((int64_t)I.flat_den * (int64_t)mn * nreach >= (int64_t)I.flat_num * (int64_t)tot)
+                I.flat[slot] = 1;
+            if (tot + (uint64_t)X >= 0xffffffffull) atomicOr(&I.ctr->err, kErrOverflow);
+        }
+    }
+}
+
+__global__ void __launch_bounds__(512) k_sweep_wave(const Inst* __restrict__ insts,
+                                                    const Tile* __restrict__ tiles, int ntiles)
+{
+    extern __shared__ __align__(16) char smem[];
+    const Tile tile = tiles[blockIdx.x];
+    const Inst& I = insts[tile.inst];
+    if (I.ctr->all_done) return;
+    if (I.model == 0) sweep_wave<0>(I, tile, smem);
+    else sweep_wave<1>(I, tile, smem);
+}
+
 // ------------------------------------------------------------------- merge
 // One block per (instance, window).  When all m walkers are flat:
 // ln g := mean_w ln g_w = base + 2^-(k + log2 m) sum_w H_w (exact), then the

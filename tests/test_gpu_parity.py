@@ -106,10 +106,17 @@ SMALL = [
 ]
 
 
+def _tune(rw, kind, wpb=0, graph=0, poll=8):
+    return rw.rewl_tune(wpb, graph, poll, {"auto": 0, "lane": 1, "wave": 2}[kind])
+
+
+@pytest.mark.parametrize("kind", ["lane", "wave"])
 @pytest.mark.parametrize("kw", SMALL, ids=lambda kw: f"{kw['model']}-L{kw['L']}-h{kw['n_windows']}-m{kw['m']}")
-def test_lockstep_small(rw, kw):
+def test_lockstep_small(rw, kw, kind):
     steps = 40 if kw["X"] > 1 else 3000
-    _lockstep(rw, kw, steps, every=1 if kw["X"] > 1 else 500)
+    gpu, _, _ = _lockstep(rw, kw, steps, tune=_tune(rw, kind), every=1 if kw["X"] > 1 else 500)
+    wave_ok = kw["model"] == "potts" or kw["L"] <= 64
+    assert gpu.info()["sweep_kind"] == (kind if wave_ok else "lane")
 
 
 def test_config1_full_run_bitwise(rw):
@@ -132,8 +139,9 @@ def test_config1_full_run_bitwise(rw):
     dict(model="ising", L=64, n_windows=16, m=64, kfinal=27, X=10000, seed=1),      # config 2
     dict(model="potts", q=10, L=32, n_windows=32, m=128, kfinal=27, X=10000, seed=1),  # config 3
 ], ids=["config2-ising64", "config3-potts32"])
-def test_full_size_configs_first_intervals(rw, kw):
-    _lockstep(rw, kw, 2)
+@pytest.mark.parametrize("kind", ["auto", "lane"])
+def test_full_size_configs_first_intervals(rw, kw, kind):
+    _lockstep(rw, kw, 2, tune=_tune(rw, kind))
 
 
 def test_walkers_per_block_does_not_change_results(rw):
@@ -142,11 +150,12 @@ def test_walkers_per_block_does_not_change_results(rw):
     orc = O.Sim(oc)
     orc.run(12)
     ref = orc.state()
-    for wpb in (1, 4, 16, 32):
-        g = rw.Rewl([gc], tune=rw.rewl_tune(wpb, 0, 4, 0))
-        assert g.info()["walkers_per_block"] == wpb
+    for kind, wpb in (("lane", 1), ("lane", 4), ("lane", 16), ("lane", 32), ("wave", 1), ("wave", 2),
+                      ("wave", 8)):
+        g = rw.Rewl([gc], tune=_tune(rw, kind, wpb, poll=4))
+        assert g.info()["walkers_per_block"] == wpb and g.info()["sweep_kind"] == kind
         g.run(12)
-        assert_same(g.state(), ref, f"wpb={wpb}")
+        assert_same(g.state(), ref, f"{kind} wpb={wpb}")
         g.close()
 
 
@@ -154,7 +163,7 @@ def test_graph_replay_matches_oracle(rw):
     """The interval captured once as a HIP graph and replayed, host syncs in between."""
     kw = dict(model="ising", L=16, n_windows=6, m=4, kfinal=10, X=1500, seed=31)
     gc, oc = _cfgs(rw, **kw)
-    g = rw.Rewl([gc], tune=rw.rewl_tune(0, 1, 5, 0))
+    g = rw.Rewl([gc], tune=_tune(rw, "auto", graph=1, poll=5))
     orc = O.Sim(oc)
     for _ in range(8):
         g.run(10)
@@ -168,13 +177,15 @@ def test_batch_of_mixed_instances(rw):
            dict(model="potts", q=10, L=16, n_windows=8, m=4, kfinal=10, X=2000, seed=102),
            dict(model="potts", q=4, L=12, n_windows=3, m=16, kfinal=10, X=2000, seed=103),
            dict(model="ising", L=24, n_windows=8, m=2, kfinal=10, X=2000, seed=104)]
-    g = rw.Rewl([rw.make_config(**kw) for kw in kws])
-    orcs = [O.Sim(O.make_config(**kw)) for kw in kws]
-    for _ in range(3):
-        g.run(7)
-        for i, o in enumerate(orcs):
-            o.run(7)
-            assert_same(g.state(i), o.state(), f"instance {i}")
+    for kind in ("lane", "wave"):
+        g = rw.Rewl([rw.make_config(**kw) for kw in kws], tune=_tune(rw, kind))
+        orcs = [O.Sim(O.make_config(**kw)) for kw in kws]
+        for _ in range(3):
+            g.run(7)
+            for i, o in enumerate(orcs):
+                o.run(7)
+                assert_same(g.state(i), o.state(), f"{kind} instance {i}")
+        g.close()
 
 
 def test_checkpoint_restore_bitwise(rw):
