@@ -36,6 +36,8 @@ PEAK_HBM = 8.0e12
 OPS_PER_ATTEMPT = {"ising": 30, "potts": 37}
 
 WORKLOADS = {
+    "ising8": dict(model="ising", L=8, n_windows=4, m=1, kfinal=20, X=10000, seed=1,
+                   label="2D Ising L=8 periodic, 4 windows o=3/4, 1 walker/window, X=1e4, ln f to 2^-20"),
     "ising64": dict(model="ising", L=64, n_windows=16, m=64, kfinal=27, X=10000, seed=1,
                     label="2D Ising L=64 periodic, 16 windows o=3/4, 64 walkers/window, X=1e4"),
     "potts32": dict(model="potts", q=10, L=32, n_windows=32, m=128, kfinal=27, X=10000, seed=1,
@@ -71,6 +73,58 @@ def cpu_baseline(kw: dict, budget_s: float) -> dict:
                       f"after 1 warm-up interval, {dt:.1f} s"}
 
 
+def exact_ln_g(kw: dict):
+    """Exact ln g of the Ising workloads (stored values written by the exact routines)."""
+    import numpy as np
+    if kw["model"] != "ising":
+        return None
+    gold = os.path.join(ROOT, "tests", "golden")
+    path = os.path.join(gold, f"ising_L{kw['L']}_lng.txt")
+    if os.path.exists(path):
+        vals = [float(l.split()[1]) for l in open(path) if l.strip() and not l.startswith("#")]
+        return np.array(vals)
+    path = os.path.join(gold, f"ising_q2_L{kw['L']}_counts.txt")
+    if os.path.exists(path):
+        import math
+        cnt = [int(l.split()[1]) for l in open(path) if l.strip() and not l.startswith("#")]
+        return np.array([math.log(c) if c > 0 else -math.inf for c in cnt])
+    return None
+
+
+def converge(rw, kw: dict, label: str, tune, max_s: float, seed: int) -> dict:
+    """Wall time from the first interval until every window reached ln f <= 2^-kfinal."""
+    import numpy as np
+    kw = dict(kw, seed=seed)
+    cfg = rw.make_config(**kw)
+    g = rw.Rewl([cfg], tune=tune)
+    _sync()
+    t0 = time.perf_counter()
+    last = t0
+    done = False
+    while not done and time.perf_counter() - t0 < max_s:
+        done = g.run(200)
+        if time.perf_counter() - last > 10:
+            st = g.stats()
+            print(f"[converge] {time.perf_counter() - t0:.0f} s: t={st['intervals']} min k={st['min_k']} "
+                  f"windows done {st['windows_done']}/{kw['n_windows']}", file=sys.stderr, flush=True)
+            last = time.perf_counter()
+    dt = time.perf_counter() - t0
+    st = g.stats()
+    out = {"workload": label, "seed": seed, "converged": bool(done), "seconds": dt,
+           "intervals": st["intervals"], "attempts": st["attempts"], "min_k": st["min_k"],
+           "kfinal": kw["kfinal"]}
+    if done:
+        lng, join = g.concat()
+        ex = exact_ln_g(kw)
+        if ex is not None:
+            ok = np.isfinite(ex)
+            eps = np.abs(lng[ok] - ex[ok]) / np.abs(ex[ok])
+            out.update(eps_max=float(eps.max()), eps_mean=float(eps.mean()),
+                       abs_err_max=float(np.abs(lng[ok] - ex[ok]).max()))
+    g.close()
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -80,6 +134,13 @@ def main(argv=None):
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sweep", default="auto", choices=["auto", "lane", "wave"])
+    ap.add_argument("--converge", action="store_true",
+                    help="run to convergence and print time-to-converge and DOS error")
+    ap.add_argument("--max-seconds", type=float, default=600.0)
+    ap.add_argument("--seeds", default="1")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="first copy a device buffer of this size (a known-size kernel for "
+                         "calibrating HBM byte counters)")
     ap.add_argument("--wpb", type=int, default=0, help="walkers per block (0 = library choice)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
@@ -89,8 +150,24 @@ def main(argv=None):
 
     import paper_1407_5140_amd as rw
 
+    if args.calib_copy_mib:
+        import torch
+        n = args.calib_copy_mib << 20
+        src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] calibration copy of {args.calib_copy_mib} MiB done", file=sys.stderr, flush=True)
+        del src, dst
+
     kw = dict(WORKLOADS[args.workload])
     label = kw.pop("label")
+    if args.converge:
+        tune = rw.rewl_tune(args.wpb, 1, 200, {"auto": 0, "lane": 1, "wave": 2}[args.sweep])
+        for sd in [int(x) for x in args.seeds.split(",")]:
+            print(json.dumps(converge(rw, kw, label, tune, args.max_seconds, sd)), flush=True)
+        return 0
     cfg = rw.make_config(**kw)
     S = kw["n_windows"] * kw["m"]
     X = kw["X"]

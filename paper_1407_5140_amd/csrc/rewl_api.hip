@@ -668,18 +668,18 @@ rewl_status rewl_get_state(rewl_handle* H, int32_t i, uint8_t* spins, int32_t* b
                 for (int x = 0; x < L; ++x) {
                     uint8_t v;
                     if (d.model == 0)
-                        v = (uint8_t)((lat[(size_t)(y * hi.wpr + (x >> 6)) * S + sl] >> (x & 63)) & 1u);
+                        v = (uint8_t)((lat[sl * L * hi.wpr + y * hi.wpr + (x >> 6)] >> (x & 63)) & 1u);
                     else
-                        v = plat[(size_t)(y * L + x) * S + sl];
+                        v = plat[sl * N + y * L + x];
                     spins[sl * N + y * L + x] = v;
                 }
     }
     if (Hout || lng) {
         for (size_t sl = 0; sl < S; ++sl) {
-            const size_t a = sl / m, r = sl % m;
+            const size_t a = sl / m;
             const double scale = std::ldexp(1.0, -kk[a]);
             for (size_t b = 0; b < WB; ++b) {
-                const uint32_t hv = Hd[(a * WB + b) * m + r];
+                const uint32_t hv = Hd[sl * WB + b];
                 if (Hout) Hout[sl * WB + b] = hv;
                 if (lng) lng[sl * WB + b] = std::fma((double)hv, scale, base[a * WB + b]);
             }

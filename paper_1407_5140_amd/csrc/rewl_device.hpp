@@ -185,10 +185,10 @@ struct Inst {
     int64_t XP;         // row stride of the draw buffers: X rounded up to 32
     uint32_t k0, k1;
     // device arrays
-    uint64_t* lat;      // Ising: [L*wpr][S] words, bit x of row y's word = spin up
-    uint8_t* plat;      // Potts: [N][S] bytes
+    uint64_t* lat;      // Ising: [S][L*wpr] words, bit x of row y's word = spin up
+    uint8_t* plat;      // Potts: [S][N] bytes
     int32_t* bin;       // [S]   global energy bin of the slot's configuration
-    uint32_t* H;        // [h][WB][m]
+    uint32_t* H;        // [S][WB] (slot = a*m + r): walker-major
     double* base;       // [h][WB] window ln g base: ln g_w = base + 2^-k H_w
     int32_t* lo;        // [h]
     int32_t* hi;        // [h]

@@ -115,21 +115,25 @@ __device__ void sweep_tile(const Inst& I, const Tile& tile, char* smem)
         const int b = i - kPad;
         lbase[i] = (b >= 0 && b < WB) ? I.base[(size_t)a * WB + b] : __builtin_inf();
     }
-    for (int i = lane; i < (nbins << lnw); i += nthr) {
-        const int b = (i >> lnw) - kPad, l = i & (nw - 1);
-        uint32_t hv = 0;
-        if (b >= 0 && b < WB)
-            hv = I.mask[lo + b] ? I.H[((size_t)a * WB + b) * I.m + tile.r0 + l] : 0xffffffffu;
-        lH[i] = hv;
-    }
+    // global H is walker-major: H[slot][bin]; consecutive threads take consecutive bins
+    for (int l = 0; l < nw; ++l)
+        for (int i = lane; i < nbins; i += nthr) {
+            const int b = i - kPad;
+            uint32_t hv = 0;
+            if (b >= 0 && b < WB)
+                hv = I.mask[lo + b] ? I.H[(size_t)(slot0 + l) * WB + b] : 0xffffffffu;
+            lH[(i << lnw) + l] = hv;
+        }
+    // lattices are walker-major too: lat[slot][word] / plat[slot][site]
     if (MODEL == 0) {
         uint64_t* lat = (uint64_t*)latp;
-        for (int i = lane; i < ((L * WPR) << lnw); i += nthr)
-            lat[i] = I.lat[(size_t)(i >> lnw) * S + slot0 + (i & (nw - 1))];
+        const int nwords = L * WPR;
+        for (int l = 0; l < nw; ++l)
+            for (int w = lane; w < nwords; w += nthr) lat[(w << lnw) + l] = I.lat[(size_t)(slot0 + l) * nwords + w];
     } else {
         uint8_t* lat = (uint8_t*)latp;
-        for (int i = lane; i < (N << lnw); i += nthr)
-            lat[i] = I.plat[(size_t)(i >> lnw) * S + slot0 + (i & (nw - 1))];
+        for (int l = 0; l < nw; ++l)
+            for (int w = lane; w < N; w += nthr) lat[(w << lnw) + l] = I.plat[(size_t)(slot0 + l) * N + w];
     }
     __syncthreads();
 
@@ -264,19 +268,20 @@ __device__ void sweep_tile(const Inst& I, const Tile& tile, char* smem)
     __syncthreads();
 
     // ---- write back
-    for (int i = lane; i < (WB << lnw); i += nthr) {
-        const int bb = i >> lnw, l = i & (nw - 1);
-        const uint32_t hv = lH[((bb + kPad) << lnw) + l];
-        I.H[((size_t)a * WB + bb) * I.m + tile.r0 + l] = hv == 0xffffffffu ? 0u : hv;
-    }
+    for (int l = 0; l < nw; ++l)
+        for (int bb = lane; bb < WB; bb += nthr) {
+            const uint32_t hv = lH[((bb + kPad) << lnw) + l];
+            I.H[(size_t)(slot0 + l) * WB + bb] = hv == 0xffffffffu ? 0u : hv;
+        }
     if (MODEL == 0) {
         const uint64_t* lat = (const uint64_t*)latp;
-        for (int i = lane; i < ((L * WPR) << lnw); i += nthr)
-            I.lat[(size_t)(i >> lnw) * S + slot0 + (i & (nw - 1))] = lat[i];
+        const int nwords = L * WPR;
+        for (int l = 0; l < nw; ++l)
+            for (int w = lane; w < nwords; w += nthr) I.lat[(size_t)(slot0 + l) * nwords + w] = lat[(w << lnw) + l];
     } else {
         const uint8_t* lat = (const uint8_t*)latp;
-        for (int i = lane; i < (N << lnw); i += nthr)
-            I.plat[(size_t)(i >> lnw) * S + slot0 + (i & (nw - 1))] = lat[i];
+        for (int l = 0; l < nw; ++l)
+            for (int w = lane; w < N; w += nthr) I.plat[(size_t)(slot0 + l) * N + w] = lat[(w << lnw) + l];
     }
 
     // ---- flatness of each walker (Sec. II.A): min H >= num/den * mean H over
@@ -366,13 +371,13 @@ __device__ void sweep_wave(const Inst& I, const Tile& tile, char* smem)
             const int b = i - kPad;
             uint32_t hv = 0;
             if (b >= 0 && b < WB)
-                hv = I.mask[lo + b] ? I.H[((size_t)a * WB + b) * I.m + r] : 0xffffffffu;
+                hv = I.mask[lo + b] ? I.H[(size_t)slot * WB + b] : 0xffffffffu;
             lH[i] = hv;
         }
         if (MODEL == 0) {
-            if (lane < L) row = I.lat[(size_t)lane * S + slot];
+            if (lane < L) row = I.lat[(size_t)slot * L + lane];
         } else {
-            for (int i = lane; i < N; i += 64) llat[i] = I.plat[(size_t)i * S + slot];
+            for (int i = lane; i < N; i += 64) llat[i] = I.plat[(size_t)slot * N + i];
         }
     }
     __syncthreads();
@@ -480,12 +485,12 @@ __device__ void sweep_wave(const Inst& I, const Tile& tile, char* smem)
     // ---- write back
     for (int i = lane; i < WB; i += 64) {
         const uint32_t hv = lH[i + kPad];
-        I.H[((size_t)a * WB + i) * I.m + r] = hv == 0xffffffffu ? 0u : hv;
+        I.H[(size_t)slot * WB + i] = hv == 0xffffffffu ? 0u : hv;
     }
     if (MODEL == 0) {
-        if (lane < L) I.lat[(size_t)lane * S + slot] = row;
+        if (lane < L) I.lat[(size_t)slot * L + lane] = row;
     } else {
-        for (int i = lane; i < N; i += 64) I.plat[(size_t)i * S + slot] = llat[i];
+        for (int i = lane; i < N; i += 64) I.plat[(size_t)slot * N + i] = llat[i];
     }
     if (lane == 0) {
         I.bin[slot] = b - kPad + lo;
@@ -554,11 +559,11 @@ __global__ void __launch_bounds__(256) k_merge(const Inst* __restrict__ insts,
     const int WB = I.WB, m = I.m, k = I.k[a], lo = I.lo[a];
     const int sh = k + I.log2m;
     double* base = I.base + (size_t)a * WB;
-    uint32_t* H = I.H + (size_t)a * WB * m;
+    uint32_t* H = I.H + (size_t)a * m * WB;                    // the window's walkers, H[r][bin]
     double mn = __builtin_inf(), mx = 0.0;
     for (int b = tid; b < WB; b += blockDim.x) {
         uint64_t s = 0;
-        for (int r = 0; r < m; ++r) s += H[(size_t)b * m + r];
+        for (int r = 0; r < m; ++r) s += H[(size_t)r * WB + b];
         const double nb = base[b] + __builtin_ldexp((double)s, -sh);
         base[b] = nb;
         if (I.mask[lo + b]) mn = nb < mn ? nb : mn;
@@ -631,28 +636,40 @@ __global__ void __launch_bounds__(256) k_exchange(const Inst* __restrict__ insts
         const double sb = __builtin_ldexp(1.0, -I.k[a + 1]);
         const double* ba = I.base + (size_t)a * WB;
         const double* bb = I.base + (size_t)(a + 1) * WB;
-        const uint32_t* Ha = I.H + (size_t)a * WB * m;
-        const uint32_t* Hb = I.H + (size_t)(a + 1) * WB * m;
-        auto gi = [&](int bin) { return __builtin_fma((double)Ha[(size_t)(bin - loa) * m + r], sa, ba[bin - loa]); };
-        auto gj = [&](int bin) { return __builtin_fma((double)Hb[(size_t)(bin - lob) * m + rj], sb, bb[bin - lob]); };
+        const uint32_t* Hi = I.H + (size_t)i * WB;
+        const uint32_t* Hj = I.H + (size_t)j * WB;
+        auto gi = [&](int bin) { return __builtin_fma((double)Hi[bin - loa], sa, ba[bin - loa]); };
+        auto gj = [&](int bin) { return __builtin_fma((double)Hj[bin - lob], sb, bb[bin - lob]); };
         const double delta = (gi(bi) - gi(bj)) + (gj(bj) - gj(bi));
         acc = accept_full(delta, u53_of(draw(I.k0, I.k1, (uint64_t)t, (uint32_t)i, kTagExchange)));
     }
     if (acc) {
         if (I.model == 0) {
             const int nwords = I.L * I.wpr;
+            uint64_t* pi = I.lat + (size_t)i * nwords;
+            uint64_t* pj = I.lat + (size_t)j * nwords;
             for (int w = 0; w < nwords; ++w) {
-                uint64_t* p = I.lat + (size_t)w * I.S;
-                const uint64_t x = p[i];
-                p[i] = p[j];
-                p[j] = x;
+                const uint64_t x = pi[w];
+                pi[w] = pj[w];
+                pj[w] = x;
             }
         } else {
-            for (int w = 0; w < I.N; ++w) {
-                uint8_t* p = I.plat + (size_t)w * I.S;
-                const uint8_t x = p[i];
-                p[i] = p[j];
-                p[j] = x;
+            uint32_t* pi = (uint32_t*)(I.plat + (size_t)i * I.N);   // N % 4 == 0 or byte tail
+            uint32_t* pj = (uint32_t*)(I.plat + (size_t)j * I.N);
+            if ((I.N & 3) == 0) {
+                for (int w = 0; w < (I.N >> 2); ++w) {
+                    const uint32_t x = pi[w];
+                    pi[w] = pj[w];
+                    pj[w] = x;
+                }
+            } else {
+                uint8_t* bi8 = I.plat + (size_t)i * I.N;
+                uint8_t* bj8 = I.plat + (size_t)j * I.N;
+                for (int w = 0; w < I.N; ++w) {
+                    const uint8_t x = bi8[w];
+                    bi8[w] = bj8[w];
+                    bj8[w] = x;
+                }
             }
         }
         I.bin[i] = bj;
@@ -690,11 +707,11 @@ __device__ int lattice_bin(const Inst& I, int slot)
             const int xr = x + 1 == L ? 0 : x + 1, yd = y + 1 == L ? 0 : y + 1;
             if (I.model == 0) {
                 auto sp = [&](int yy, int xx) {
-                    return (int)(I.lat[(size_t)(yy * I.wpr + (xx >> 6)) * I.S + slot] >> (xx & 63)) & 1;
+                    return (int)(I.lat[(size_t)slot * L * I.wpr + yy * I.wpr + (xx >> 6)] >> (xx & 63)) & 1;
                 };
                 broken += (sp(y, x) != sp(y, xr)) + (sp(y, x) != sp(yd, x));
             } else {
-                auto sp = [&](int yy, int xx) { return (int)I.plat[(size_t)(yy * L + xx) * I.S + slot]; };
+                auto sp = [&](int yy, int xx) { return (int)I.plat[(size_t)slot * I.N + yy * L + xx]; };
                 broken += (sp(y, x) != sp(y, xr)) + (sp(y, x) != sp(yd, x));
             }
         }
@@ -727,10 +744,10 @@ __global__ void k_init(const Inst* __restrict__ insts, const int32_t* __restrict
                     const bool up = upper ? ((x + y) & 1) == 0 : true;
                     word |= (uint64_t)up << xb;
                 }
-                I.lat[(size_t)(y * I.wpr + wi) * I.S + slot] = word;
+                I.lat[(size_t)slot * L * I.wpr + y * I.wpr + wi] = word;
             }
     } else {
-        for (int s = 0; s < N; ++s) I.plat[(size_t)s * I.S + slot] = 0;
+        for (int s = 0; s < N; ++s) I.plat[(size_t)slot * N + s] = 0;
     }
     int b = lattice_bin(I, slot);
     auto dist = [&](int bb) { return bb < wlo ? wlo - bb : (bb > whi ? bb - whi : 0); };
@@ -749,14 +766,14 @@ __global__ void k_init(const Inst* __restrict__ insts, const int32_t* __restrict
         int nv = 0;
         if (I.model == 0) {
             auto sp = [&](int yy, int xx) {
-                return (int)(I.lat[(size_t)(yy * I.wpr + (xx >> 6)) * I.S + slot] >> (xx & 63)) & 1;
+                return (int)(I.lat[(size_t)slot * L * I.wpr + yy * I.wpr + (xx >> 6)] >> (xx & 63)) & 1;
             };
             const int s = sp(r, c);
             const int ones = sp(ru, c) + sp(rd, c) + sp(r, cl) + sp(r, cr);
             const int al = s ? ones : 4 - ones;
             nb = b + al - 2;
         } else {
-            auto sp = [&](int yy, int xx) { return (int)I.plat[(size_t)(yy * L + xx) * I.S + slot]; };
+            auto sp = [&](int yy, int xx) { return (int)I.plat[(size_t)slot * N + yy * L + xx]; };
             const int s = sp(r, c);
             nv = s + 1 + (int)(((uint64_t)x.y * (uint64_t)(I.q - 1)) >> 32);
             nv = nv >= I.q ? nv - I.q : nv;
@@ -770,10 +787,10 @@ __global__ void k_init(const Inst* __restrict__ insts, const int32_t* __restrict
         }
         if (dist(nb) <= dist(b)) {
             if (I.model == 0) {
-                uint64_t* p = I.lat + (size_t)(r * I.wpr + (c >> 6)) * I.S + slot;
+                uint64_t* p = I.lat + (size_t)slot * L * I.wpr + r * I.wpr + (c >> 6);
                 *p ^= 1ull << (c & 63);
             } else {
-                I.plat[(size_t)site * I.S + slot] = (uint8_t)nv;
+                I.plat[(size_t)slot * N + site] = (uint8_t)nv;
             }
             b = nb;
         }
