@@ -35,14 +35,18 @@ PEAK_HBM = 8.0e12
 # ln g update (3).  Potts adds 2 reads and 5 comparisons for the new state.
 OPS_PER_ATTEMPT = {"ising": 30, "potts": 37}
 
-WORKLOADS = {
-    "ising8": dict(model="ising", L=8, n_windows=4, m=1, kfinal=20, X=10000, seed=1,
-                   label="2D Ising L=8 periodic, 4 windows o=3/4, 1 walker/window, X=1e4, ln f to 2^-20"),
-    "ising64": dict(model="ising", L=64, n_windows=16, m=64, kfinal=27, X=10000, seed=1,
-                    label="2D Ising L=64 periodic, 16 windows o=3/4, 64 walkers/window, X=1e4"),
-    "potts32": dict(model="potts", q=10, L=32, n_windows=32, m=128, kfinal=27, X=10000, seed=1,
-                    label="2D 10-state Potts L=32 periodic, 32 windows o=3/4, 128 walkers/window, X=1e4"),
+LABELS = {
+    "ising8": "2D Ising L=8 periodic, 4 windows o=3/4, 1 walker/window, X=1e4, ln f to 2^-20",
+    "ising64": "2D Ising L=64 periodic, 16 windows o=3/4, 64 walkers/window, X=1e4",
+    "potts32": "2D 10-state Potts L=32 periodic, 32 windows o=3/4, 128 walkers/window, X=1e4",
+    "batch64": "64 independent REWL instances: Ising L 16-64 and Potts q 4/8/10 L 16-32, "
+               "8-32 windows, 32-128 walkers/window, X=1e4",
 }
+
+
+def workload(name: str) -> list:
+    from paper_1407_5140_amd import workloads as W
+    return W.batch() if name == "batch64" else [W.single(name)]
 
 
 def _sync():
@@ -54,22 +58,23 @@ def _sync():
         pass
 
 
-def cpu_baseline(kw: dict, budget_s: float) -> dict:
+def cpu_baseline(kws: list, budget_s: float) -> dict:
     """The oracle as it stands, all host threads, a bounded number of intervals."""
     import oracle as O
-    cfg = O.make_config(**{k: v for k, v in kw.items() if k != "label"})
-    sim = O.Sim(cfg)
+    sims = [O.Sim(O.make_config(**kw)) for kw in kws]
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
     t0 = time.perf_counter()
-    sim.run(1, threads=threads)
+    for s in sims:
+        s.run(1, threads=threads)
     one = time.perf_counter() - t0
     n = max(1, min(200, int(budget_s / max(one, 1e-3))))
     t0 = time.perf_counter()
-    sim.run(n, threads=threads)
+    for s in sims:
+        s.run(n, threads=threads)
     dt = time.perf_counter() - t0
-    S = kw["n_windows"] * kw["m"]
-    return {"value": n * S * kw["X"] / dt, "unit": "attempts/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n} exchange intervals ({n * S * kw['X']:.3g} attempts) of the same workload "
+    att = n * sum(kw["n_windows"] * kw["m"] * kw["X"] for kw in kws)
+    return {"value": att / dt, "unit": "attempts/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n} exchange intervals ({att:.3g} attempts) of the same workload "
                       f"after 1 warm-up interval, {dt:.1f} s"}
 
 
@@ -130,7 +135,8 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="ising64", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="ising64", choices=sorted(LABELS))
+    ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sweep", default="auto", choices=["auto", "lane", "wave"])
@@ -161,23 +167,23 @@ def main(argv=None):
         print(f"[bench] calibration copy of {args.calib_copy_mib} MiB done", file=sys.stderr, flush=True)
         del src, dst
 
-    kw = dict(WORKLOADS[args.workload])
-    label = kw.pop("label")
+    kws = workload(args.workload)
+    label = LABELS[args.workload]
     if args.converge:
-        tune = rw.rewl_tune(args.wpb, 1, 200, {"auto": 0, "lane": 1, "wave": 2}[args.sweep])
+        tune = rw.make_tune(args.sweep, args.wpb, 1, 200)
         for sd in [int(x) for x in args.seeds.split(",")]:
-            print(json.dumps(converge(rw, kw, label, tune, args.max_seconds, sd)), flush=True)
+            print(json.dumps(converge(rw, kws[0], label, tune, args.max_seconds, sd)), flush=True)
         return 0
-    cfg = rw.make_config(**kw)
-    S = kw["n_windows"] * kw["m"]
-    X = kw["X"]
+    cfgs = [rw.make_config(**kw) for kw in kws]
+    S = sum(kw["n_windows"] * kw["m"] for kw in kws)
+    att_step = sum(kw["n_windows"] * kw["m"] * kw["X"] for kw in kws)
     t_create = time.perf_counter()
-    tune = rw.rewl_tune(args.wpb, 0, 1 << 20, {"auto": 0, "lane": 1, "wave": 2}[args.sweep])
-    g = rw.Rewl([cfg], tune=tune)
+    tune = rw.make_tune(args.sweep, args.wpb, 0, 1 << 20, autotune=1 if args.autotune else 0)
+    g = rw.Rewl(cfgs, tune=tune)
     t_create = time.perf_counter() - t_create
     info = g.info()
     print(f"[bench] {label}: {S} walkers, {info['sweep_kind']} sweep, walkers/block {info['walkers_per_block']}, "
-          f"LDS {info['lds_bytes']} B, create {t_create:.2f} s", file=sys.stderr, flush=True)
+          f"LDS {info['lds_bytes']} B, tune {g.tune()}, create {t_create:.2f} s", file=sys.stderr, flush=True)
 
     rw.rewl_run_exact(g.h, args.warmup)
     rw.rewl_set_timing(g.h, True)
@@ -189,11 +195,11 @@ def main(argv=None):
     dt = time.perf_counter() - t0
     st1 = g.stats()
     rw.rewl_set_timing(g.h, False)
-    attempts = args.steps * S * X
+    attempts = args.steps * att_step
     value = attempts / dt
     sweep_ms = (st1["sweep_ms"] - st0["sweep_ms"]) / args.steps
     interval_ms = (st1["interval_ms"] - st0["interval_ms"]) / args.steps
-    ops = OPS_PER_ATTEMPT[kw["model"]] * S * X
+    ops = sum(OPS_PER_ATTEMPT[kw["model"]] * kw["n_windows"] * kw["m"] * kw["X"] for kw in kws)
     achieved = ops / (sweep_ms * 1e-3)
     print(f"[bench] {args.steps} intervals in {dt:.3f} s: {value:.4g} attempts/s; sweep "
           f"{sweep_ms:.3f} ms/launch, interval {interval_ms:.3f} ms (events)", file=sys.stderr,
@@ -212,20 +218,19 @@ def main(argv=None):
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": label, "walkers": S, "attempts_per_step": S * X,
+        "config": {"workload": label, "walkers": S, "attempts_per_step": att_step,
                    "sweep": info["sweep_kind"], "walkers_per_block": info["walkers_per_block"]},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
                      "unit": "Tops/s", "frac": achieved / PEAK_LANE_OPS, "traffic": None,
                      "kernel": "k_sweep_wave" if info["sweep_kind"] == "wave" else "k_sweep",
                      "kernel_ms": sweep_ms,
-                     "ops_per_attempt": OPS_PER_ATTEMPT[kw["model"]]},
-        "sweep_attempts_per_s": S * X / (sweep_ms * 1e-3),
+                     "ops_per_attempt": ops / att_step},
+        "sweep_attempts_per_s": att_step / (sweep_ms * 1e-3),
     }
     g.close()
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on the host cores", file=sys.stderr, flush=True)
-        kwl = dict(WORKLOADS[args.workload])
-        out["cpu_baseline"] = cpu_baseline(kwl, args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(kws, args.cpu_budget)
     print(json.dumps(out), flush=True)
     return 0
 

@@ -71,6 +71,10 @@ typedef struct {
     int32_t use_graph;          /* 1: replay the interval as a captured HIP graph        */
     int32_t poll_every;         /* intervals between host checks of the done flags      */
     int32_t sweep_kind;         /* REWL_SWEEP_*, applied to every instance that allows it */
+    int32_t lds_target_kb;      /* LANE: cap on a tile's LDS (sets walkers per block and
+                                   so blocks per CU); 0 = the device limit               */
+    int32_t autotune;           /* 1: time candidate variants / LDS targets on the real
+                                   batch for two intervals at creation, keep the fastest */
 } rewl_tune;
 
 typedef struct rewl_handle rewl_handle;
@@ -154,6 +158,9 @@ rewl_status rewl_restore(rewl_handle* h, const void* buf, size_t len);
 
 void rewl_destroy(rewl_handle* h);
 const char* rewl_last_error(void);
+
+/* The tuning in effect (after autotuning, the winner). */
+rewl_status rewl_get_tune(rewl_handle* h, rewl_tune* out);
 
 /* Number of instances, and for one instance the sweep variant chosen
  * (REWL_SWEEP_LANE / _WAVE), walkers per block and LDS bytes per block.       */

@@ -330,6 +330,8 @@ orc_sim* orc_create(const orc_config* c, const uint8_t* mask, const double* init
             s->lng[(size_t)sl * s->WB + b] = init_lng ? init_lng[s->lo[a] + b] : 0.0;
     }
     int stuck = 0, imax = 0;
+    /* walkers are independent: each drives only its own lattice */
+#pragma omp parallel for schedule(dynamic, 16) reduction(| : stuck) reduction(max : imax)
     for (int sl = 0; sl < s->S; ++sl) {
         int64_t used = init_slot(s, sl);
         if (used < 0) stuck = 1;

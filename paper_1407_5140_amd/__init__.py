@@ -48,7 +48,14 @@ REWL_SWEEP_AUTO, REWL_SWEEP_LANE, REWL_SWEEP_WAVE = 0, 1, 2
 
 class rewl_tune(ctypes.Structure):
     _fields_ = [("walkers_per_block", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-                ("poll_every", ctypes.c_int32), ("sweep_kind", ctypes.c_int32)]
+                ("poll_every", ctypes.c_int32), ("sweep_kind", ctypes.c_int32),
+                ("lds_target_kb", ctypes.c_int32), ("autotune", ctypes.c_int32)]
+
+
+def make_tune(kind="auto", walkers_per_block=0, use_graph=0, poll_every=8, lds_target_kb=0,
+              autotune=0) -> rewl_tune:
+    return rewl_tune(walkers_per_block, use_graph, poll_every,
+                     {"auto": 0, "lane": 1, "wave": 2}[kind], lds_target_kb, autotune)
 
 
 class rewl_stats(ctypes.Structure):
@@ -77,6 +84,7 @@ _sigs = {
     "rewl_restore": ([_vp, _vp, ctypes.c_size_t], ctypes.c_int),
     "rewl_destroy": ([_vp], None),
     "rewl_info": ([_vp, ctypes.c_int32, _vp, _vp, _vp, _vp], ctypes.c_int),
+    "rewl_get_tune": ([_vp, _P(rewl_tune)], ctypes.c_int),
     "rewl_probe_accept": ([_vp, _vp, ctypes.c_int32, _vp], ctypes.c_int),
     "rewl_probe_philox": ([_vp, ctypes.c_int32, _vp], ctypes.c_int),
 }
@@ -218,6 +226,12 @@ def rewl_info(h, instance: int = 0) -> dict:
                 walkers_per_block=w.value, lds_bytes=lds.value)
 
 
+def rewl_get_tune(h) -> dict:
+    t = rewl_tune()
+    _check(_lib.rewl_get_tune(h, ctypes.byref(t)), "rewl_get_tune")
+    return {f: getattr(t, f) for f, _ in rewl_tune._fields_}
+
+
 def rewl_probe_accept(delta, u53) -> np.ndarray:
     d = np.ascontiguousarray(delta, dtype=np.float64)
     u = np.ascontiguousarray(u53, dtype=np.uint64)
@@ -278,3 +292,6 @@ class Rewl:
 
     def info(self, i: int = 0) -> dict:
         return rewl_info(self.h, i)
+
+    def tune(self) -> dict:
+        return rewl_get_tune(self.h)

@@ -396,7 +396,9 @@ static rewl_status create_impl(const rewl_config* cfgs, int32_t n, void* hip_str
             int want = H->tune.walkers_per_block > 0 ? H->tune.walkers_per_block : 64;
             int wpb = 1;
             while (wpb * 2 <= std::min(want, std::min(64, hi.m))) wpb *= 2;
-            while (wpb > 1 && sweep_lds_bytes(c.model, c.L, hi.wpr, hi.WB, wpb) > (size_t)lds_limit) wpb /= 2;
+            size_t cap = (size_t)lds_limit;
+            if (H->tune.lds_target_kb > 0) cap = std::min(cap, (size_t)H->tune.lds_target_kb * 1024);
+            while (wpb > 1 && sweep_lds_bytes(c.model, c.L, hi.wpr, hi.WB, wpb) > cap) wpb /= 2;
             hi.wpb = wpb;
             hi.lds = sweep_lds_bytes(c.model, c.L, hi.wpr, hi.WB, wpb);
             H->max_lds = std::max(H->max_lds, hi.lds);
@@ -529,10 +531,71 @@ static rewl_status create_impl(const rewl_config* cfgs, int32_t n, void* hip_str
     return REWL_OK;
 }
 
+// Autotuner: build the batch with each candidate tuning, time two intervals of
+// the real workload (state and draws are those of the run itself), keep the
+// fastest.  Every candidate computes bit-identical results; only speed differs.
+static rewl_status autotune(const rewl_config* cfgs, int32_t n, void* hip_stream,
+                            const rewl_tune& base, rewl_tune* best)
+{
+    std::vector<rewl_tune> cand;
+    bool all_wave = true;
+    for (int i = 0; i < n; ++i) all_wave = all_wave && (cfgs[i].model == 1 || cfgs[i].L <= 64);
+    for (int kb : {40, 53, 80, 0}) {
+        rewl_tune t = base;
+        t.sweep_kind = REWL_SWEEP_LANE;
+        t.walkers_per_block = 0;
+        t.lds_target_kb = kb;
+        t.autotune = 0;
+        cand.push_back(t);
+    }
+    if (all_wave)
+        for (int g : {1, 4}) {
+            rewl_tune t = base;
+            t.sweep_kind = REWL_SWEEP_WAVE;
+            t.walkers_per_block = g;
+            t.lds_target_kb = 0;
+            t.autotune = 0;
+            cand.push_back(t);
+        }
+    double best_ms = 1e300;
+    *best = cand[0];
+    for (const rewl_tune& t : cand) {
+        rewl_handle* h = nullptr;
+        rewl_status s = create_impl(cfgs, n, hip_stream, &t, &h);
+        if (s != REWL_OK) continue;                      // e.g. out of memory: skip
+        h->timing = true;
+        s = rewl_run_exact(h, 2);
+        const double ms = h->interval_ms;
+        rewl_destroy(h);
+        if (s == REWL_OK && ms < best_ms) {
+            best_ms = ms;
+            *best = t;
+        }
+    }
+    return best_ms < 1e300 ? REWL_OK : fail(REWL_E_DEVICE, "autotune: no candidate ran");
+}
+
 rewl_status rewl_batch_create(const rewl_config* cfgs, int32_t n, void* hip_stream,
                               const rewl_tune* tune, rewl_handle** out)
 {
+    if (tune && tune->autotune) {
+        for (int i = 0; i < n && cfgs; ++i) {
+            rewl_status s = validate(cfgs[i]);
+            if (s != REWL_OK) return s;
+        }
+        rewl_tune best;
+        rewl_status s = autotune(cfgs, n, hip_stream, *tune, &best);
+        if (s != REWL_OK) return s;
+        return create_impl(cfgs, n, hip_stream, &best, out);
+    }
     return create_impl(cfgs, n, hip_stream, tune, out);
+}
+
+rewl_status rewl_get_tune(rewl_handle* H, rewl_tune* out)
+{
+    if (!H || !out) return fail(REWL_E_INVALID, "null argument");
+    *out = H->tune;
+    return REWL_OK;
 }
 
 rewl_status rewl_create(const rewl_config* cfg, void* hip_stream, rewl_handle** out)

@@ -13,8 +13,12 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 @pytest.fixture(scope="module")
 def rw():
-    from paper_1407_5140_amd.build import build_library
-    build_library(force=False)
+    import importlib.util
+    spec = importlib.util.spec_from_file_location(
+        "_rewl_build", os.path.join(ROOT, "paper_1407_5140_amd", "build.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    mod.build_library(force=False)
     import paper_1407_5140_amd as rw
     return rw
 

@@ -107,7 +107,7 @@ SMALL = [
 
 
 def _tune(rw, kind, wpb=0, graph=0, poll=8):
-    return rw.rewl_tune(wpb, graph, poll, {"auto": 0, "lane": 1, "wave": 2}[kind])
+    return rw.make_tune(kind, wpb, graph, poll)
 
 
 @pytest.mark.parametrize("kind", ["lane", "wave"])
@@ -228,3 +228,19 @@ def test_bad_warm_start_rejected(rw):
     bad = np.full(65, 0.1)                       # not a multiple of 2^-20
     with pytest.raises(rw.RewlError):
         g.set_initial_lng(bad)
+
+
+def test_batch64_first_interval_autotuned(rw):
+    """The 64-instance uneven batch, autotuned, one interval: every instance bit-exact."""
+    from paper_1407_5140_amd import workloads as W
+    kws = W.batch()
+    g = rw.Rewl([rw.make_config(**kw) for kw in kws], tune=rw.make_tune(autotune=1))
+    chosen = g.tune()
+    assert chosen["autotune"] == 0 and chosen["sweep_kind"] in (1, 2)
+    orcs = [O.Sim(O.make_config(**kw)) for kw in kws]
+    for i, o in enumerate(orcs):
+        assert_same(g.state(i), o.state(), f"batch instance {i} after init")
+    g.run(1)
+    for i, o in enumerate(orcs):
+        o.run(1)
+        assert_same(g.state(i), o.state(), f"batch instance {i} after 1 interval")
