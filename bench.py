@@ -44,6 +44,32 @@ LABELS = {
 }
 
 
+# rocprofv3 summaries holding the HBM byte counters of a workload's sweep kernel
+PROFILES = {"ising64": "k_sweep_wave_ising_L64.txt", "potts32": "k_sweep_potts_q10_L32.txt"}
+KERNEL_SOURCES = ("paper_1407_5140_amd/csrc/rewl_kernels.hip", "paper_1407_5140_amd/csrc/rewl_device.hpp")
+
+
+def profiled_traffic(wl: str, kernel: str):
+    """(read, written) HBM bytes per launch from the committed counter summary, or
+    None when there is none or the kernel sources changed since it was taken."""
+    import hashlib
+    fn = PROFILES.get(wl)
+    path = os.path.join(ROOT, "profiles", fn) if fn else ""
+    if not fn or not os.path.exists(path):
+        return None
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    for line in open(path):
+        tok = line.split()
+        if len(tok) == 5 and tok[0] == "traffic" and tok[1] == kernel:
+            kv = dict(t.split("=", 1) for t in tok[2:])
+            if kv["source_sha256"] == h.hexdigest()[:16]:
+                return int(kv["read_bytes"]), int(kv["write_bytes"])
+    return None
+
+
 def workload(name: str) -> list:
     from paper_1407_5140_amd import workloads as W
     return W.batch() if name == "batch64" else [W.single(name)]
@@ -67,7 +93,7 @@ def cpu_baseline(kws: list, budget_s: float) -> dict:
     for s in sims:
         s.run(1, threads=threads)
     one = time.perf_counter() - t0
-    n = max(1, min(200, int(budget_s / max(one, 1e-3))))
+    n = max(1, min(5000, int(budget_s / max(one, 1e-3))))
     t0 = time.perf_counter()
     for s in sims:
         s.run(n, threads=threads)
@@ -145,8 +171,8 @@ def main(argv=None):
     ap.add_argument("--max-seconds", type=float, default=600.0)
     ap.add_argument("--seeds", default="1")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
-                    help="first copy a device buffer of this size (a known-size kernel for "
-                         "calibrating HBM byte counters)")
+                    help="only copy a device buffer of this size and exit (a kernel of known "
+                         "traffic for scaling the HBM byte counters)")
     ap.add_argument("--wpb", type=int, default=0, help="walkers per block (0 = library choice)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
@@ -165,7 +191,7 @@ def main(argv=None):
         dst.copy_(src)
         torch.cuda.synchronize()
         print(f"[bench] calibration copy of {args.calib_copy_mib} MiB done", file=sys.stderr, flush=True)
-        del src, dst
+        return 0
 
     kws = workload(args.workload)
     label = LABELS[args.workload]
@@ -200,6 +226,8 @@ def main(argv=None):
     sweep_ms = (st1["sweep_ms"] - st0["sweep_ms"]) / args.steps
     interval_ms = (st1["interval_ms"] - st0["interval_ms"]) / args.steps
     ops = sum(OPS_PER_ATTEMPT[kw["model"]] * kw["n_windows"] * kw["m"] * kw["X"] for kw in kws)
+    kernel = "k_sweep_wave" if info["sweep_kind"] == "wave" else "k_sweep"
+    traffic = profiled_traffic(args.workload, kernel)
     achieved = ops / (sweep_ms * 1e-3)
     print(f"[bench] {args.steps} intervals in {dt:.3f} s: {value:.4g} attempts/s; sweep "
           f"{sweep_ms:.3f} ms/launch, interval {interval_ms:.3f} ms (events)", file=sys.stderr,
@@ -221,8 +249,10 @@ def main(argv=None):
         "config": {"workload": label, "walkers": S, "attempts_per_step": att_step,
                    "sweep": info["sweep_kind"], "walkers_per_block": info["walkers_per_block"]},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
-                     "unit": "Tops/s", "frac": achieved / PEAK_LANE_OPS, "traffic": None,
-                     "kernel": "k_sweep_wave" if info["sweep_kind"] == "wave" else "k_sweep",
+                     "unit": "Tops/s", "frac": achieved / PEAK_LANE_OPS,
+                     "traffic": None if traffic is None else sum(traffic),
+                     "traffic_read_write": traffic,
+                     "kernel": kernel,
                      "kernel_ms": sweep_ms,
                      "ops_per_attempt": ops / att_step},
         "sweep_attempts_per_s": att_step / (sweep_ms * 1e-3),
