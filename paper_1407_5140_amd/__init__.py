@@ -87,6 +87,19 @@ _sigs = {
     "rewl_get_tune": ([_vp, _P(rewl_tune)], ctypes.c_int),
     "rewl_probe_accept": ([_vp, _vp, ctypes.c_int32, _vp], ctypes.c_int),
     "rewl_probe_philox": ([_vp, ctypes.c_int32, _vp], ctypes.c_int),
+    # density-of-states network (include/rewl_mlp.h)
+    "mlp_last_error": ([], ctypes.c_char_p),
+    "mlp_create": ([_vp, _vp, _P(_vp)], ctypes.c_int),
+    "mlp_destroy": ([_vp], None),
+    "mlp_n_params": ([_vp, _P(ctypes.c_int64)], ctypes.c_int),
+    "mlp_get_params": ([_vp, _vp, ctypes.c_size_t], ctypes.c_int),
+    "mlp_set_params": ([_vp, _vp, ctypes.c_size_t], ctypes.c_int),
+    "mlp_infer": ([_vp, _vp, _vp, ctypes.c_int32], ctypes.c_int),
+    "mlp_grad": ([_vp, _vp, _vp, ctypes.c_int32, _vp, _vp], ctypes.c_int),
+    "mlp_fit": ([_vp, _vp, _vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64, ctypes.c_float,
+                 ctypes.c_uint32, _vp], ctypes.c_int),
+    "mlp_warm_table": ([_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _vp], ctypes.c_int),
+    "mlp_probe_gemm": ([_vp, _vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _vp], ctypes.c_int),
 }
 for _name, (_args, _res) in _sigs.items():
     _f = getattr(_lib, _name)
@@ -99,6 +112,18 @@ EXPORTED = tuple(_sigs)
 def _check(status: int, where: str) -> None:
     if status != REWL_OK:
         raise RewlError(status, where)
+
+
+class MlpError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        msg = _lib.mlp_last_error().decode(errors="replace")
+        super().__init__(f"{where}: REWL_E_{_STATUS.get(status, status)} ({status}): {msg}")
+        self.status = status
+
+
+def _mcheck(status: int, where: str) -> None:
+    if status != REWL_OK:
+        raise MlpError(status, where)
 
 
 def _p(a: np.ndarray):
@@ -295,3 +320,91 @@ class Rewl:
 
     def tune(self) -> dict:
         return rewl_get_tune(self.h)
+
+
+# ------------------------------------------------------------ DOS network
+class mlp_config(ctypes.Structure):
+    _fields_ = [("in_dim", ctypes.c_int32), ("hidden", ctypes.c_int32), ("layers", ctypes.c_int32),
+                ("max_batch", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+
+
+MODELS = {"ising": 0, "potts": 1}
+
+
+def _rows(a, width: int) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float32).reshape(-1, width)
+
+
+def mlp_probe_gemm(A, B) -> np.ndarray:
+    a = np.ascontiguousarray(A, dtype=np.float32)
+    b = np.ascontiguousarray(B, dtype=np.float32)
+    M_, K = a.shape
+    K2, N_ = b.shape
+    if K != K2:
+        raise ValueError("inner dimensions differ")
+    c = np.empty((M_, N_), np.float32)
+    _mcheck(_lib.mlp_probe_gemm(_p(a), _p(b), M_, N_, K, _p(c)), "mlp_probe_gemm")
+    return c
+
+
+class Mlp:
+    """The density-of-states network: parameters, training and inference live on
+    the device (include/rewl_mlp.h); rows and results cross as numpy arrays."""
+
+    def __init__(self, in_dim=3, hidden=256, layers=3, max_batch=4096, seed=1, stream=None):
+        self.cfg = mlp_config(in_dim, hidden, layers, max_batch, seed)
+        h = _vp()
+        _mcheck(_lib.mlp_create(ctypes.byref(self.cfg), stream, ctypes.byref(h)), "mlp_create")
+        self.h = h
+        n = ctypes.c_int64()
+        _mcheck(_lib.mlp_n_params(self.h, ctypes.byref(n)), "mlp_n_params")
+        self.n_params = n.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def params(self) -> np.ndarray:
+        out = np.empty(self.n_params, np.float32)
+        _mcheck(_lib.mlp_get_params(self.h, _p(out), out.size), "mlp_get_params")
+        return out
+
+    def set_params(self, p) -> None:
+        a = np.ascontiguousarray(p, dtype=np.float32)
+        _mcheck(_lib.mlp_set_params(self.h, _p(a), a.size), "mlp_set_params")
+
+    def infer(self, x) -> np.ndarray:
+        xr = _rows(x, self.cfg.in_dim)
+        y = np.empty(xr.shape[0], np.float32)
+        _mcheck(_lib.mlp_infer(self.h, _p(xr), _p(y), xr.shape[0]), "mlp_infer")
+        return y
+
+    def grad(self, x, t):
+        xr = _rows(x, self.cfg.in_dim)
+        tr = np.ascontiguousarray(t, dtype=np.float32).reshape(-1)
+        g = np.empty(self.n_params, np.float32)
+        loss = ctypes.c_float()
+        _mcheck(_lib.mlp_grad(self.h, _p(xr), _p(tr), xr.shape[0], _p(g), ctypes.byref(loss)), "mlp_grad")
+        return g, loss.value
+
+    def fit(self, x, t, steps: int, batch: int = 4096, lr: float = 1e-3, seed: int = 1) -> float:
+        """Adam steps on minibatches drawn from the rows (x, t); returns the last batch loss."""
+        xr = _rows(x, self.cfg.in_dim)
+        tr = np.ascontiguousarray(t, dtype=np.float32).reshape(-1)
+        loss = ctypes.c_float()
+        _mcheck(_lib.mlp_fit(self.h, _p(xr), _p(tr), xr.shape[0], batch, steps, lr, seed,
+                             ctypes.byref(loss)), "mlp_fit")
+        return loss.value
+
+    def warm_table(self, model: str, q: int, L: int) -> np.ndarray:
+        W = L * L + 1 if model == "ising" else 2 * L * L + 1
+        out = np.empty(W, np.float64)
+        _mcheck(_lib.mlp_warm_table(self.h, MODELS[model], q, L, _p(out)), "mlp_warm_table")
+        return out

@@ -8,8 +8,9 @@ import subprocess
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "librewl.so")
-SOURCES = ["csrc/rewl_api.hip"]
-DEPS = ["csrc/rewl_api.hip", "csrc/rewl_kernels.hip", "csrc/rewl_device.hpp"]
+SOURCES = ["csrc/rewl_api.hip", "csrc/mlp.hip"]
+DEPS = ["csrc/rewl_api.hip", "csrc/rewl_kernels.hip", "csrc/rewl_device.hpp", "csrc/mlp.hip"]
+HEADERS = ["rewl.h", "rewl_mlp.h"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-shared", "-fPIC", "-Wall",
@@ -32,8 +33,8 @@ def build_library(force: bool = True, verbose: bool = False) -> str:
     """Compile librewl.so; with force=False only when a source is newer."""
     if not force and os.path.exists(LIB):
         newest = max(os.path.getmtime(os.path.join(PKG, d)) for d in DEPS)
-        hdr = os.path.join(ROOT, "include", "rewl.h")
-        newest = max(newest, os.path.getmtime(hdr))
+        for hdr in HEADERS:
+            newest = max(newest, os.path.getmtime(os.path.join(ROOT, "include", hdr)))
         if os.path.getmtime(LIB) >= newest:
             return LIB
     tmp = LIB + ".tmp"

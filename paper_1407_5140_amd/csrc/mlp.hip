@@ -1,0 +1,582 @@
+// mlp.hip -- a small MLP that learns ln g(E)/N, trained and evaluated on gfx950.
+//
+// Network: x = (E/N, 1/L, q) -> `layers` hidden layers of width H with the erf
+// GELU -> one linear output (ln g / N).  Weights are kept in FP32 (master copy,
+// Adam moments) and in BF16 for the matrix cores; every H x H product is a
+// BF16 MFMA GEMM (v_mfma_f32_32x32x16_bf16) with FP32 accumulation.  The first
+// layer (K = 3) and the output layer (N = 1) are plain FP32 kernels.
+//
+// Flat parameter order: W1[in][H], b1[H], then for each further hidden layer
+// W[H][H], b[H], then w_out[H], b_out[1] (row-major, W[i][j]: input i -> unit j).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/rewl_mlp.h"
+
+namespace {
+
+thread_local std::string g_mlp_err;
+
+rewl_status mfail(rewl_status s, const std::string& m)
+{
+    g_mlp_err = m;
+    return s;
+}
+
+#define MLP_TRY(expr)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess) return mfail(REWL_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ float gelu(float a)
+{
+    return 0.5f * a * (1.0f + erff(a * 0.70710678118654752f));
+}
+__device__ __forceinline__ float gelu_grad(float a)
+{
+    return 0.5f * (1.0f + erff(a * 0.70710678118654752f)) +
+           a * 0.39894228040143268f * expf(-0.5f * a * a);
+}
+
+// ---------------------------------------------------------------- GEMM
+// C[M][N] = sum_k A(i,k) B(k,j) with A(i,k) = A[i*lda + k] (or A[k*lda + i] if
+// ta) and B(k,j) = B[k*ldb + j] (or B[j*ldb + k] if tb); BF16 inputs, FP32
+// accumulation.  One wave per 32 x 32 output tile; M, N multiples of 32, K of 16.
+// Operand layout of v_mfma_f32_32x32x16_bf16: lane l supplies A rows i = l%32,
+// k = 8*(l/32) .. +7 and B columns j = l%32, same k; the 16 accumulators of lane
+// l hold C(8*(r/4) + 4*(l/32) + r%4, l%32), r = 0..15.
+enum Epi : int {
+    kEpiStore = 0,        // C = acc (FP32)
+    kEpiBiasGelu = 1,     // pre = acc + bias[j] (FP32 out), act = gelu(pre) (BF16 out)
+    kEpiGeluGrad = 2,     // d = acc * gelu'(pre) (FP32 and BF16 out)
+};
+
+__global__ void __launch_bounds__(64) k_gemm(const __bf16* __restrict__ A, int lda, int ta,
+                                             const __bf16* __restrict__ B, int ldb, int tb,
+                                             int M, int N, int K, int epi,
+                                             float* __restrict__ C, int ldc,
+                                             const float* __restrict__ bias,
+                                             const float* __restrict__ pre,
+                                             __bf16* __restrict__ out16)
+{
+    const int lane = threadIdx.x;
+    const int i0 = blockIdx.y * 32, j0 = blockIdx.x * 32;
+    const int li = lane & 31, kg = (lane >> 5) * 8;
+    f32x16 acc = {};
+    for (int k0 = 0; k0 < K; k0 += 16) {
+        bf16x8 av, bv;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int k = k0 + kg + u;
+            av[u] = ta ? A[(size_t)k * lda + i0 + li] : A[(size_t)(i0 + li) * lda + k];
+            bv[u] = tb ? B[(size_t)(j0 + li) * ldb + k] : B[(size_t)k * ldb + j0 + li];
+        }
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int i = i0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int j = j0 + li;
+        const size_t o = (size_t)i * ldc + j;
+        const float v = acc[r];
+        if (epi == kEpiStore) {
+            C[o] = v;
+        } else if (epi == kEpiBiasGelu) {
+            const float p = v + bias[j];
+            C[o] = p;
+            out16[o] = (__bf16)gelu(p);
+        } else {
+            const float d = v * gelu_grad(pre[o]);
+            C[o] = d;
+            out16[o] = (__bf16)d;
+        }
+    }
+}
+
+// first layer: pre = x W1 + b1 (K = in_dim), act = gelu(pre) in BF16
+__global__ void k_layer_in(const float* __restrict__ x, int in_dim, const float* __restrict__ W,
+                           const float* __restrict__ b, int H, int B, float* __restrict__ pre,
+                           __bf16* __restrict__ act)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= B * H) return;
+    const int r = idx / H, j = idx - r * H;
+    float s = b[j];
+    for (int i = 0; i < in_dim; ++i) s += x[r * in_dim + i] * W[i * H + j];
+    pre[idx] = s;
+    act[idx] = (__bf16)gelu(s);
+}
+
+// output layer y = act . w + b0 (FP32), one thread per row
+__global__ void k_layer_out(const __bf16* __restrict__ act, const float* __restrict__ w,
+                            const float* __restrict__ b0, int H, int B, float* __restrict__ y)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= B) return;
+    float s = b0[0];
+    for (int j = 0; j < H; ++j) s += (float)act[(size_t)r * H + j] * w[j];
+    y[r] = s;
+}
+
+// loss pieces: dy = 2 (y - t) / B for rows < nvalid, 0 for padding; loss sum
+__global__ void k_loss(const float* __restrict__ y, const float* __restrict__ t, int B, int nvalid,
+                       float* __restrict__ dy, float* __restrict__ loss)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= B) return;
+    float d = 0.f;
+    if (r < nvalid) {
+        d = y[r] - t[r];
+        atomicAdd(loss, d * d / (float)nvalid);
+        d = 2.f * d / (float)nvalid;
+    }
+    dy[r] = d;
+}
+
+// back through the output layer: d_pre = dy[r] w[j] gelu'(pre), grads of w_out, b_out
+__global__ void k_back_out(const float* __restrict__ dy, const float* __restrict__ w,
+                           const float* __restrict__ pre, int H, int B, float* __restrict__ dpre,
+                           __bf16* __restrict__ dpre16)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= B * H) return;
+    const int r = idx / H, j = idx - r * H;
+    const float d = dy[r] * w[j] * gelu_grad(pre[idx]);
+    dpre[idx] = d;
+    dpre16[idx] = (__bf16)d;
+}
+
+// column sums over the batch: out[j] = sum_r M[r][j] (and optionally weighted by v[r] x act)
+__global__ void k_colsum(const float* __restrict__ Mx, int H, int B, float* __restrict__ out)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= H) return;
+    float s = 0.f;
+    for (int r = 0; r < B; ++r) s += Mx[(size_t)r * H + j];
+    out[j] = s;
+}
+
+// grad of w_out: g[j] = sum_r dy[r] act[r][j]; grad of b_out = sum dy
+__global__ void k_grad_out(const float* __restrict__ dy, const __bf16* __restrict__ act, int H,
+                           int B, float* __restrict__ gw, float* __restrict__ gb)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j > H) return;
+    float s = 0.f;
+    if (j == H) {
+        for (int r = 0; r < B; ++r) s += dy[r];
+        gb[0] = s;
+        return;
+    }
+    for (int r = 0; r < B; ++r) s += dy[r] * (float)act[(size_t)r * H + j];
+    gw[j] = s;
+}
+
+// grad of W1: g[i][j] = sum_r x[r][i] d[r][j]
+__global__ void k_grad_in(const float* __restrict__ x, int in_dim, const float* __restrict__ d,
+                          int H, int B, float* __restrict__ g)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= in_dim * H) return;
+    const int i = idx / H, j = idx - i * H;
+    float s = 0.f;
+    for (int r = 0; r < B; ++r) s += x[r * in_dim + i] * d[(size_t)r * H + j];
+    g[idx] = s;
+}
+
+// Adam (Kingma & Ba) on the FP32 master weights, BF16 copies refreshed
+__global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, int n, float lr, float b1, float b2, float eps,
+                       float c1, float c2, __bf16* __restrict__ p16, const int* __restrict__ map16)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float pi = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    p[i] = pi;
+    const int o = map16[i];
+    if (o >= 0) p16[o] = (__bf16)pi;
+}
+
+__global__ void k_to_bf16(const float* __restrict__ a, __bf16* __restrict__ b, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = (__bf16)a[i];
+}
+
+// gather a minibatch: rows idx = floor(u * n) from a counter-based hash
+__global__ void k_gather(const float* __restrict__ X, const float* __restrict__ Y, int in_dim,
+                         int n, int B, uint64_t step, uint32_t seed, float* __restrict__ xb,
+                         float* __restrict__ yb)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= B) return;
+    // splitmix64 of (seed, step, r): any fixed hash serves, only the sample order depends on it
+    uint64_t z = ((uint64_t)seed << 32) ^ (step * 0x9E3779B97F4A7C15ull) ^ (uint64_t)r * 0xD1B54A32D192ED03ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    const int k = (int)(((z >> 32) * (uint64_t)n) >> 32);
+    for (int i = 0; i < in_dim; ++i) xb[r * in_dim + i] = X[(size_t)k * in_dim + i];
+    yb[r] = Y[k];
+}
+
+}  // namespace
+
+struct mlp_handle {
+    mlp_config cfg;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int H = 0, nl = 0, P = 0, Bmax = 0;
+    std::vector<int> off_W, off_b;     // offsets into the flat parameter vector
+    int off_wout = 0, off_bout = 0, n16 = 0;
+    std::vector<int> off16;            // BF16 copy offsets of the H x H matrices
+    float *p = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;
+    __bf16* p16 = nullptr;
+    int* map16 = nullptr;
+    std::vector<float*> pre;           // [nl] B x H pre-activations (FP32)
+    std::vector<__bf16*> act;          // [nl] B x H activations (BF16)
+    float *dpre = nullptr, *dtmp = nullptr, *y = nullptr, *dy = nullptr, *loss = nullptr;
+    __bf16 *d16a = nullptr, *d16b = nullptr;
+    float *xb = nullptr, *yb = nullptr;
+    float *dx = nullptr, *dt = nullptr;   // training rows of the last mlp_fit call
+    int64_t data_cap = 0;
+    int64_t steps = 0;
+    std::vector<void*> allocs;
+    template <class T>
+    rewl_status alloc(T** q, size_t n)
+    {
+        void* r = nullptr;
+        if (hipMalloc(&r, std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess)
+            return mfail(REWL_E_NOMEM, "hipMalloc failed");
+        allocs.push_back(r);
+        *q = (T*)r;
+        return REWL_OK;
+    }
+};
+
+namespace {
+
+inline dim3 grid1(int n, int b = 256) { return dim3((n + b - 1) / b); }
+
+// forward pass of B rows (B a multiple of 32) already in xb; y written
+void forward(mlp_handle* h, const float* x, int B)
+{
+    const int H = h->H;
+    hipLaunchKernelGGL(k_layer_in, grid1(B * H), dim3(256), 0, h->stream, x, h->cfg.in_dim,
+                       h->p + h->off_W[0], h->p + h->off_b[0], H, B, h->pre[0], h->act[0]);
+    for (int l = 1; l < h->nl; ++l)
+        hipLaunchKernelGGL(k_gemm, dim3(H / 32, B / 32), dim3(64), 0, h->stream, h->act[l - 1], H, 0,
+                           h->p16 + h->off16[l], H, 0, B, H, H, (int)kEpiBiasGelu, h->pre[l], H,
+                           h->p + h->off_b[l], (const float*)nullptr, h->act[l]);
+    hipLaunchKernelGGL(k_layer_out, grid1(B), dim3(256), 0, h->stream, h->act[h->nl - 1],
+                       h->p + h->off_wout, h->p + h->off_bout, H, B, h->y);
+}
+
+// backward after forward(); gradients into h->g (loss value in h->loss)
+void backward(mlp_handle* h, const float* x, const float* t, int B, int nvalid)
+{
+    const int H = h->H, nl = h->nl;
+    (void)hipMemsetAsync(h->loss, 0, sizeof(float), h->stream);
+    hipLaunchKernelGGL(k_loss, grid1(B), dim3(256), 0, h->stream, h->y, t, B, nvalid, h->dy, h->loss);
+    hipLaunchKernelGGL(k_grad_out, grid1(H + 1), dim3(256), 0, h->stream, h->dy, h->act[nl - 1], H, B,
+                       h->g + h->off_wout, h->g + h->off_bout);
+    hipLaunchKernelGGL(k_back_out, grid1(B * H), dim3(256), 0, h->stream, h->dy, h->p + h->off_wout,
+                       h->pre[nl - 1], H, B, h->dpre, h->d16a);
+    __bf16* dcur = h->d16a;
+    __bf16* dnext = h->d16b;
+    for (int l = nl - 1; l >= 1; --l) {
+        // dW_l = act_{l-1}^T d_l  (K = B), db_l = column sums of d_l
+        hipLaunchKernelGGL(k_gemm, dim3(H / 32, H / 32), dim3(64), 0, h->stream, h->act[l - 1], H, 1,
+                           dcur, H, 0, H, H, B, (int)kEpiStore, h->g + h->off_W[l], H,
+                           (const float*)nullptr, (const float*)nullptr, (__bf16*)nullptr);
+        hipLaunchKernelGGL(k_colsum, grid1(H), dim3(256), 0, h->stream, h->dpre, H, B,
+                           h->g + h->off_b[l]);
+        // d_{l-1} = (d_l W_l^T) * gelu'(pre_{l-1})
+        hipLaunchKernelGGL(k_gemm, dim3(H / 32, B / 32), dim3(64), 0, h->stream, dcur, H, 0,
+                           h->p16 + h->off16[l], H, 1, B, H, H, (int)kEpiGeluGrad, h->dtmp, H,
+                           (const float*)nullptr, h->pre[l - 1], dnext);
+        std::swap(h->dpre, h->dtmp);
+        std::swap(dcur, dnext);
+    }
+    hipLaunchKernelGGL(k_grad_in, grid1(h->cfg.in_dim * H), dim3(256), 0, h->stream, x, h->cfg.in_dim,
+                       h->dpre, H, B, h->g + h->off_W[0]);
+    hipLaunchKernelGGL(k_colsum, grid1(H), dim3(256), 0, h->stream, h->dpre, H, B, h->g + h->off_b[0]);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mlp_last_error(void) { return g_mlp_err.c_str(); }
+
+void mlp_destroy(mlp_handle* h)
+{
+    if (!h) return;
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    for (void* q : h->allocs) (void)hipFree(q);
+    if (h->dx) (void)hipFree(h->dx);
+    if (h->dt) (void)hipFree(h->dt);
+    if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+    delete h;
+}
+
+rewl_status mlp_create(const mlp_config* c, void* hip_stream, mlp_handle** out)
+{
+    if (!c || !out) return mfail(REWL_E_INVALID, "null argument");
+    *out = nullptr;
+    if (c->in_dim < 1 || c->in_dim > 16 || c->hidden < 32 || c->hidden % 32 || c->hidden > 4096 ||
+        c->layers < 1 || c->layers > 16 || c->max_batch < 32 || c->max_batch > (1 << 20))
+        return mfail(REWL_E_INVALID, "need 1<=in_dim<=16, hidden a multiple of 32, 1<=layers<=16, max_batch>=32");
+    mlp_handle* h = new mlp_handle();
+    h->cfg = *c;
+    h->H = c->hidden;
+    h->nl = c->layers;
+    h->Bmax = (c->max_batch + 31) / 32 * 32;
+    const int H = h->H;
+    int off = 0;
+    h->off_W.push_back(off);
+    off += c->in_dim * H;
+    h->off_b.push_back(off);
+    off += H;
+    h->off16.push_back(-1);
+    for (int l = 1; l < h->nl; ++l) {
+        h->off_W.push_back(off);
+        h->off16.push_back(h->n16);
+        h->n16 += H * H;
+        off += H * H;
+        h->off_b.push_back(off);
+        off += H;
+    }
+    h->off_wout = off;
+    off += H;
+    h->off_bout = off;
+    off += 1;
+    h->P = off;
+    auto bail = [&](rewl_status s) {
+        mlp_destroy(h);
+        return s;
+    };
+    if (hip_stream) h->stream = (hipStream_t)hip_stream;
+    else {
+        if (hipStreamCreate(&h->stream) != hipSuccess) return bail(mfail(REWL_E_DEVICE, "hipStreamCreate"));
+        h->own_stream = true;
+    }
+    rewl_status s = REWL_OK;
+    const size_t BH = (size_t)h->Bmax * H;
+    if (s == REWL_OK) s = h->alloc(&h->p, h->P);
+    if (s == REWL_OK) s = h->alloc(&h->g, h->P);
+    if (s == REWL_OK) s = h->alloc(&h->m, h->P);
+    if (s == REWL_OK) s = h->alloc(&h->v, h->P);
+    if (s == REWL_OK) s = h->alloc(&h->p16, h->n16);
+    if (s == REWL_OK) s = h->alloc(&h->map16, h->P);
+    h->pre.assign(h->nl, nullptr);
+    h->act.assign(h->nl, nullptr);
+    for (int l = 0; l < h->nl && s == REWL_OK; ++l) {
+        s = h->alloc(&h->pre[l], BH);
+        if (s == REWL_OK) s = h->alloc(&h->act[l], BH);
+    }
+    if (s == REWL_OK) s = h->alloc(&h->dpre, BH);
+    if (s == REWL_OK) s = h->alloc(&h->dtmp, BH);
+    if (s == REWL_OK) s = h->alloc(&h->d16a, BH);
+    if (s == REWL_OK) s = h->alloc(&h->d16b, BH);
+    if (s == REWL_OK) s = h->alloc(&h->y, h->Bmax);
+    if (s == REWL_OK) s = h->alloc(&h->dy, h->Bmax);
+    if (s == REWL_OK) s = h->alloc(&h->loss, 1);
+    if (s == REWL_OK) s = h->alloc(&h->xb, (size_t)h->Bmax * c->in_dim);
+    if (s == REWL_OK) s = h->alloc(&h->yb, h->Bmax);
+    if (s != REWL_OK) return bail(s);
+    // initial weights: uniform(-1/sqrt(fan_in), 1/sqrt(fan_in)) from a fixed hash, biases 0
+    std::vector<float> p0(h->P, 0.f);
+    std::vector<int> map(h->P, -1);
+    uint64_t z = c->seed * 0x9E3779B97F4A7C15ull + 1;
+    auto uni = [&]() {
+        z += 0x9E3779B97F4A7C15ull;
+        uint64_t r = z;
+        r = (r ^ (r >> 30)) * 0xBF58476D1CE4E5B9ull;
+        r = (r ^ (r >> 27)) * 0x94D049BB133111EBull;
+        r ^= r >> 31;
+        return (float)((r >> 11) * (1.0 / 9007199254740992.0)) * 2.f - 1.f;
+    };
+    for (int i = 0; i < c->in_dim * H; ++i) p0[i] = uni() / std::sqrt((float)c->in_dim);
+    for (int l = 1; l < h->nl; ++l)
+        for (int i = 0; i < H * H; ++i) {
+            p0[h->off_W[l] + i] = uni() / std::sqrt((float)H);
+            map[h->off_W[l] + i] = h->off16[l] + i;
+        }
+    for (int j = 0; j < H; ++j) p0[h->off_wout + j] = uni() / std::sqrt((float)H);
+    if (hipMemcpy(h->p, p0.data(), h->P * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(h->map16, map.data(), h->P * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(h->m, 0, h->P * 4) != hipSuccess || hipMemset(h->v, 0, h->P * 4) != hipSuccess)
+        return bail(mfail(REWL_E_DEVICE, "initial upload failed"));
+    for (int l = 1; l < h->nl; ++l)
+        hipLaunchKernelGGL(k_to_bf16, grid1(H * H), dim3(256), 0, h->stream, h->p + h->off_W[l],
+                           h->p16 + h->off16[l], H * H);
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return bail(mfail(REWL_E_DEVICE, "init failed"));
+    *out = h;
+    return REWL_OK;
+}
+
+rewl_status mlp_n_params(const mlp_handle* h, int64_t* n)
+{
+    if (!h || !n) return mfail(REWL_E_INVALID, "null argument");
+    *n = h->P;
+    return REWL_OK;
+}
+
+rewl_status mlp_get_params(const mlp_handle* h, float* host, size_t n)
+{
+    if (!h || !host || n != (size_t)h->P) return mfail(REWL_E_INVALID, "need n = parameter count");
+    MLP_TRY(hipMemcpyAsync(host, h->p, n * 4, hipMemcpyDeviceToHost, h->stream));
+    MLP_TRY(hipStreamSynchronize(h->stream));
+    return REWL_OK;
+}
+
+rewl_status mlp_set_params(mlp_handle* h, const float* host, size_t n)
+{
+    if (!h || !host || n != (size_t)h->P) return mfail(REWL_E_INVALID, "need n = parameter count");
+    MLP_TRY(hipMemcpyAsync(h->p, host, n * 4, hipMemcpyHostToDevice, h->stream));
+    for (int l = 1; l < h->nl; ++l)
+        hipLaunchKernelGGL(k_to_bf16, grid1(h->H * h->H), dim3(256), 0, h->stream, h->p + h->off_W[l],
+                           h->p16 + h->off16[l], h->H * h->H);
+    MLP_TRY(hipStreamSynchronize(h->stream));
+    return REWL_OK;
+}
+
+// Forward over host rows x[B][in_dim] -> y[B], in chunks of max_batch rows.
+rewl_status mlp_infer(mlp_handle* h, const float* x, float* y, int32_t B)
+{
+    if (!h || (B > 0 && (!x || !y)) || B < 0) return mfail(REWL_E_INVALID, "bad arguments");
+    const int in = h->cfg.in_dim;
+    for (int r0 = 0; r0 < B; r0 += h->Bmax) {
+        const int nb = std::min(h->Bmax, B - r0);
+        const int Bp = (nb + 31) / 32 * 32;
+        MLP_TRY(hipMemsetAsync(h->xb, 0, (size_t)Bp * in * 4, h->stream));
+        MLP_TRY(hipMemcpyAsync(h->xb, x + (size_t)r0 * in, (size_t)nb * in * 4, hipMemcpyHostToDevice, h->stream));
+        forward(h, h->xb, Bp);
+        MLP_TRY(hipMemcpyAsync(y + r0, h->y, nb * 4, hipMemcpyDeviceToHost, h->stream));
+        MLP_TRY(hipStreamSynchronize(h->stream));
+    }
+    MLP_TRY(hipGetLastError());
+    return REWL_OK;
+}
+
+// Loss and gradient of the flat parameter vector on host rows.
+rewl_status mlp_grad(mlp_handle* h, const float* x, const float* t, int32_t B, float* grad_host, float* loss)
+{
+    if (!h || !x || !t || B < 1 || B > h->Bmax) return mfail(REWL_E_INVALID, "need 1 <= B <= max_batch");
+    const int in = h->cfg.in_dim, Bp = (B + 31) / 32 * 32;
+    MLP_TRY(hipMemsetAsync(h->xb, 0, (size_t)Bp * in * 4, h->stream));
+    MLP_TRY(hipMemsetAsync(h->yb, 0, (size_t)Bp * 4, h->stream));
+    MLP_TRY(hipMemcpyAsync(h->xb, x, (size_t)B * in * 4, hipMemcpyHostToDevice, h->stream));
+    MLP_TRY(hipMemcpyAsync(h->yb, t, (size_t)B * 4, hipMemcpyHostToDevice, h->stream));
+    forward(h, h->xb, Bp);
+    backward(h, h->xb, h->yb, Bp, B);
+    MLP_TRY(hipGetLastError());
+    if (grad_host) MLP_TRY(hipMemcpyAsync(grad_host, h->g, h->P * 4, hipMemcpyDeviceToHost, h->stream));
+    if (loss) MLP_TRY(hipMemcpyAsync(loss, h->loss, 4, hipMemcpyDeviceToHost, h->stream));
+    MLP_TRY(hipStreamSynchronize(h->stream));
+    return REWL_OK;
+}
+
+// `steps` Adam steps on minibatches of B rows sampled from n host rows (the
+// rows are uploaded once per call into a device buffer the handle keeps).
+rewl_status mlp_fit(mlp_handle* h, const float* x, const float* t, int64_t n, int32_t B, int64_t steps,
+                    float lr, uint32_t seed, float* last_loss)
+{
+    if (!h || !x || !t || n < 1 || n > INT32_MAX || B < 32 || B > h->Bmax || B % 32 || steps < 0)
+        return mfail(REWL_E_INVALID, "need 1 <= n < 2^31 rows, B a multiple of 32 in [32, max_batch]");
+    const int in = h->cfg.in_dim;
+    if (n > h->data_cap) {
+        if (h->dx) (void)hipFree(h->dx);
+        if (h->dt) (void)hipFree(h->dt);
+        h->dx = h->dt = nullptr;
+        h->data_cap = 0;
+        MLP_TRY(hipMalloc(&h->dx, (size_t)n * in * 4));
+        MLP_TRY(hipMalloc(&h->dt, (size_t)n * 4));
+        h->data_cap = n;
+    }
+    MLP_TRY(hipMemcpyAsync(h->dx, x, (size_t)n * in * 4, hipMemcpyHostToDevice, h->stream));
+    MLP_TRY(hipMemcpyAsync(h->dt, t, (size_t)n * 4, hipMemcpyHostToDevice, h->stream));
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    for (int64_t s = 0; s < steps; ++s) {
+        hipLaunchKernelGGL(k_gather, grid1(B), dim3(256), 0, h->stream, h->dx, h->dt, in, (int)n, B,
+                           (uint64_t)h->steps, seed, h->xb, h->yb);
+        forward(h, h->xb, B);
+        backward(h, h->xb, h->yb, B, B);
+        h->steps += 1;
+        const float c1 = 1.f - std::pow(b1, (float)h->steps), c2 = 1.f - std::pow(b2, (float)h->steps);
+        hipLaunchKernelGGL(k_adam, grid1(h->P), dim3(256), 0, h->stream, h->p, h->g, h->m, h->v, h->P,
+                           lr, b1, b2, eps, c1, c2, h->p16, h->map16);
+    }
+    MLP_TRY(hipGetLastError());
+    if (last_loss) MLP_TRY(hipMemcpyAsync(last_loss, h->loss, 4, hipMemcpyDeviceToHost, h->stream));
+    MLP_TRY(hipStreamSynchronize(h->stream));
+    return REWL_OK;
+}
+
+// Warm-start table for a model: ln g(E) = N * net(E/N, 1/L, q) at every bin,
+// rounded to a multiple of 2^-16 (keeps the REWL arithmetic exact).
+rewl_status mlp_warm_table(mlp_handle* h, int32_t model, int32_t q, int32_t L, double* lng_host)
+{
+    if (!h || !lng_host || L < 2 || L > 4096 || (model != 0 && model != 1))
+        return mfail(REWL_E_INVALID, "bad arguments");
+    if (h->cfg.in_dim != 3) return mfail(REWL_E_INVALID, "warm tables need in_dim = 3");
+    const int N = L * L, W = model == 0 ? N + 1 : 2 * N + 1;
+    std::vector<float> xh((size_t)W * 3), yh(W);
+    for (int b = 0; b < W; ++b) {
+        const double E = model == 0 ? 4.0 * b - 2.0 * N : (double)b - 2.0 * N;
+        xh[3 * b + 0] = (float)(E / N);
+        xh[3 * b + 1] = (float)(1.0 / L);
+        xh[3 * b + 2] = (float)(model == 0 ? 2 : q);
+    }
+    rewl_status s = mlp_infer(h, xh.data(), yh.data(), W);
+    if (s != REWL_OK) return s;
+    for (int b = 0; b < W; ++b) lng_host[b] = std::nearbyint((double)yh[b] * N * 65536.0) / 65536.0;
+    return REWL_OK;
+}
+
+// Diagnostic: the BF16 MFMA GEMM on host data, C = A B (A: M x K, B: K x N).
+rewl_status mlp_probe_gemm(const float* A, const float* B, int32_t M, int32_t N, int32_t K, float* C)
+{
+    if (!A || !B || !C || M < 32 || N < 32 || K < 16 || M % 32 || N % 32 || K % 16)
+        return mfail(REWL_E_INVALID, "M, N multiples of 32, K of 16");
+    std::vector<__bf16> a16((size_t)M * K), b16((size_t)K * N);
+    for (size_t i = 0; i < a16.size(); ++i) a16[i] = (__bf16)A[i];
+    for (size_t i = 0; i < b16.size(); ++i) b16[i] = (__bf16)B[i];
+    __bf16 *da = nullptr, *db = nullptr;
+    float* dc = nullptr;
+    MLP_TRY(hipMalloc(&da, a16.size() * 2));
+    MLP_TRY(hipMalloc(&db, b16.size() * 2));
+    MLP_TRY(hipMalloc(&dc, (size_t)M * N * 4));
+    hipError_t e = hipMemcpy(da, a16.data(), a16.size() * 2, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(db, b16.data(), b16.size() * 2, hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_gemm, dim3(N / 32, M / 32), dim3(64), 0, 0, da, K, 0, db, N, 0, M, N, K,
+                           (int)kEpiStore, dc, N, (const float*)nullptr, (const float*)nullptr,
+                           (__bf16*)nullptr);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpy(C, dc, (size_t)M * N * 4, hipMemcpyDeviceToHost);
+    (void)hipFree(da);
+    (void)hipFree(db);
+    (void)hipFree(dc);
+    if (e != hipSuccess) return mfail(REWL_E_DEVICE, hipGetErrorString(e));
+    return REWL_OK;
+}
+
+}  // extern "C"

@@ -1,4 +1,4 @@
-"""The C-ABI library: it loads, exports every symbol include/rewl.h declares, and
+"""The C-ABI library: it loads, exports every symbol include/*.h declares, and
 its pure-host calls (layout, mask, validation) agree with the paper's example and
 reject bad input before touching the device.  No GPU needed."""
 import ctypes
@@ -24,14 +24,19 @@ def rw():
 
 
 def _declared():
-    with open(os.path.join(ROOT, "include", "rewl.h")) as f:
-        txt = f.read()
-    return sorted(set(re.findall(r"^\s*(?:rewl_status|void|const char\*)\s+(rewl_\w+)\s*\(", txt, re.M)))
+    names = set()
+    for hdr in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if hdr.endswith(".h"):
+            with open(os.path.join(ROOT, "include", hdr)) as f:
+                txt = f.read()
+            names |= set(re.findall(r"^\s*(?:rewl_status|void|const char\*)\s+((?:rewl|mlp)_\w+)\s*\(",
+                                    txt, re.M))
+    return sorted(names)
 
 
 def test_library_exports_every_declared_symbol(rw):
     names = _declared()
-    assert len(names) >= 15
+    assert len(names) >= 25 and any(n.startswith("mlp_") for n in names)
     lib = ctypes.CDLL(rw.LIB_PATH)
     for n in names:
         assert hasattr(lib, n), n
