@@ -61,7 +61,7 @@ typedef struct {
 /* Sweep variants.  LANE: one walker per lane, draws precomputed for the whole
  * interval by a separate kernel (suits batches of many thousands of walkers).
  * WAVE: one walker per wave, the chain on wave-uniform values, the lanes draw
- * the next 64 attempts (suits few walkers; Ising needs L <= 64).               */
+ * the next 64 attempts (suits few walkers; needs Ising L <= 64, Potts N <= 4096). */
 enum { REWL_SWEEP_AUTO = 0, REWL_SWEEP_LANE = 1, REWL_SWEEP_WAVE = 2 };
 
 /* Optional tuning of a batch (NULL = library choice). */

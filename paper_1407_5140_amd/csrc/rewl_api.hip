@@ -385,7 +385,7 @@ static rewl_status create_impl(const rewl_config* cfgs, int32_t n, void* hip_str
         // With few walkers the chain latency, not the GPU's width, sets the rate
         // and the two are on par for Ising (measured); the lane variant is chosen
         // otherwise.
-        const bool wave_ok = c.model == 1 || c.L <= 64;
+        const bool wave_ok = c.model == 0 ? c.L <= 64 : hi.N <= kWaveMaxSites;
         int64_t total_walkers = 0;
         for (int u = 0; u < n; ++u) total_walkers += (int64_t)cfgs[u].n_windows * cfgs[u].walkers_per_window;
         hi.kind = REWL_SWEEP_LANE;

@@ -325,14 +325,20 @@ __global__ void __launch_bounds__(64) k_sweep(const Inst* __restrict__ insts,
 //   Potts: the walker's lattice is one byte per site in LDS (uniform addresses).
 // LDS: base [nbins] shared by the block's walkers (all of one window), then per
 // wave its counts H [nbins], then (Potts) per wave its lattice [N].
+// LDS of the wave variant: the window's base table (shared), then per wave its
+// histogram, its site map (one 64-bit attempt mask per site) and, for Potts,
+// its lattice.
 __host__ __device__ inline size_t wave_lds_bytes(int model, int L, int WB, int G)
 {
-    const size_t nb = (size_t)WB + 2 * kPad;
+    const size_t nb = (size_t)WB + 2 * kPad, N = (size_t)L * L;
     size_t s = nb * 8 + (size_t)G * nb * 4;
     s = (s + 7) & ~size_t(7);
-    if (model == 1) s += (size_t)G * L * L;
+    s += (size_t)G * N * 8;
+    if (model == 1) s += (size_t)G * N;
     return s;
 }
+// the site map bounds the wave variant to lattices of at most 4096 sites
+constexpr int kWaveMaxSites = 4096;
 
 __device__ __forceinline__ uint32_t rl(uint32_t v, int l)
 {
@@ -346,13 +352,39 @@ __device__ __forceinline__ double rld(double v, int l)
 {
     return __builtin_bit_cast(double, rl64(__builtin_bit_cast(uint64_t, v), l));
 }
+__device__ __forceinline__ uint32_t shfl32(uint32_t v, int src)
+{
+    return (uint32_t)__builtin_amdgcn_ds_bpermute(src << 2, (int)v);
+}
 
+// Bin change of flipping Ising spin (r, c): rows w (row r), wu (r-1), wd (r+1).
+__device__ __forceinline__ int ising_d(uint64_t w, uint64_t wu, uint64_t wd, int c, int L)
+{
+    const int cl = c == 0 ? L - 1 : c - 1, cr = c == L - 1 ? 0 : c + 1;
+    const uint32_t sp = (uint32_t)(w >> c) & 1u;
+    const uint32_t ones = ((uint32_t)(wu >> c) & 1u) + ((uint32_t)(wd >> c) & 1u) +
+                          ((uint32_t)(w >> cl) & 1u) + ((uint32_t)(w >> cr) & 1u);
+    return (sp ? (int)ones : 4 - (int)ones) - 2;
+}
+
+// Wave variant: one walker per wave.
+// * The walker's ln g and H over 64 consecutive bins live in registers, one bin
+//   per lane, so that the dependent chain of attempts touches no table memory:
+//   lane l holds bin b0 + l; the window is moved when the walker comes within
+//   four bins of its edge.
+// * Per chunk of 64 attempts the lanes draw the numbers and evaluate every
+//   attempt's bin change d on the lattice as it stands at the chunk start.  A
+//   per-site bit map in LDS gives each attempt the later attempts of the chunk
+//   whose site neighbourhood contains its site; an accepted move marks them,
+//   and a marked attempt re-evaluates d on the current lattice.
+// * The chain then only compares ln g differences (all candidate bins at once,
+//   one lane each) against the attempt's threshold.
 template <int MODEL>
 __device__ void sweep_wave(const Inst& I, const Tile& tile, char* smem)
 {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int G = tile.nw;
-    const int a = tile.window, WB = I.WB, L = I.L, S = I.S, N = I.N;
+    const int a = tile.window, WB = I.WB, L = I.L, N = I.N;
     const int nbins = WB + 2 * kPad;
     const int lo = I.lo[a];
     double* lbase = (double*)smem;
@@ -363,8 +395,9 @@ __device__ void sweep_wave(const Inst& I, const Tile& tile, char* smem)
     const bool active = wave < G;
     const int r = tile.r0 + wave, slot = a * I.m + r;
     uint32_t* lH = (uint32_t*)(lbase + nbins) + (size_t)wave * nbins;
-    uint8_t* llat = (uint8_t*)(smem + ((nbins * 8 + (size_t)G * nbins * 4 + 7) & ~size_t(7))) +
-                    (size_t)wave * N;
+    const size_t off_map = ((size_t)nbins * 8 + (size_t)G * nbins * 4 + 7) & ~size_t(7);
+    uint64_t* lmap = (uint64_t*)(smem + off_map) + (size_t)wave * N;
+    uint8_t* llat = (uint8_t*)(smem + off_map + (size_t)G * N * 8) + (size_t)wave * N;
     uint64_t row = 0;
     if (active) {
         for (int i = lane; i < nbins; i += 64) {
@@ -374,6 +407,7 @@ __device__ void sweep_wave(const Inst& I, const Tile& tile, char* smem)
                 hv = I.mask[lo + b] ? I.H[(size_t)slot * WB + b] : 0xffffffffu;
             lH[i] = hv;
         }
+        for (int i = lane; i < N; i += 64) lmap[i] = 0;
         if (MODEL == 0) {
             if (lane < L) row = I.lat[(size_t)slot * L + lane];
         } else {
@@ -386,100 +420,143 @@ __device__ void sweep_wave(const Inst& I, const Tile& tile, char* smem)
     const int k = I.k[a];
     const uint32_t inc = I.done[a] == 0 ? 1u : 0u;
     const double scale = __builtin_ldexp(1.0, -k);
+    const double incv = inc ? scale : 0.0;
     const int64_t X = I.X;
     const uint64_t T0 = (uint64_t)I.ctr->t * (uint64_t)X;
     const uint32_t q = (uint32_t)I.q, qm1 = q - 1;
-    int b = __builtin_amdgcn_readfirstlane(I.bin[slot] - lo + kPad);
-    // ln g of the walker's current state, kept incrementally: every step adds
-    // 2^-k (exact), a move replaces it by the candidate's value
-    double lngc = __builtin_fma((double)lH[b], scale, lbase[b]);
-    const double incv = inc ? scale : 0.0;
-    // lane l (l <= 8) evaluates candidate bin b + l - 4 of every attempt
-    const int cand = (lane < 8 ? lane : 8) - 4;
+    const int b = __builtin_amdgcn_readfirstlane(I.bin[slot] - lo + kPad);
+
+    // register window of the walker's table: lane l holds ln g of bin b0 + l
+    // (+inf beyond the table); the counts are recovered from it when the window
+    // moves, H = (ln g - base) 2^k, exact like every value here
+    const int b0max = nbins > 64 ? nbins - 64 : 0;
+    int b0 = b - 32 < 0 ? 0 : (b - 32 > b0max ? b0max : b - 32);
+    int idx = b - b0;                     // the walker's bin, as a lane of the window
+    const double unscale = __builtin_ldexp(1.0, k);
+    double gl;
+    auto load_window = [&]() {
+        const int i = b0 + lane;
+        gl = i < nbins ? __builtin_fma((double)lH[i], scale, lbase[i]) : __builtin_inf();
+    };
+    auto store_window = [&]() {
+        const int i = b0 + lane;
+        // pads and levels that do not occur are never visited: leave them
+        if (i >= kPad && i < kPad + WB && lH[i] != 0xffffffffu)
+            lH[i] = (uint32_t)((gl - lbase[i]) * unscale);
+    };
+    load_window();
+    double lngc = rld(gl, idx);          // ln g of the current bin (wave-uniform)
     uint32_t rlo = (uint32_t)row, rhi = (uint32_t)(row >> 32);
 
     for (int64_t j0 = 0; j0 < X; j0 += 64) {
-        // lane l draws attempt j0 + l
+        const int n = (int)((X - j0) < 64 ? (X - j0) : 64);
+        // ---- lanes: draws, sites and bin changes on the lattice at the chunk start
         const u32x4 x = draw(I.k0, I.k1, T0 + (uint64_t)(j0 + lane), (uint32_t)slot, kTagFlip);
-        const uint32_t site = (uint32_t)(((uint64_t)x.x * (uint32_t)N) >> 32);
-        const uint32_t rr = site / (uint32_t)L, cc = site - rr * (uint32_t)L;
-        uint32_t p0;
+        const int site = (int)(((uint64_t)x.x * (uint32_t)N) >> 32);
+        const int rr = site / L, cc = site - rr * L;
+        const int ru = rr == 0 ? L - 1 : rr - 1, rd = rr == L - 1 ? 0 : rr + 1;
+        const int cl = cc == 0 ? L - 1 : cc - 1, cr = cc == L - 1 ? 0 : cc + 1;
+        const int s_up = ru * L + cc, s_dn = rd * L + cc, s_lf = rr * L + cl, s_rt = rr * L + cr;
+        int d;
+        uint32_t pk;
         if (MODEL == 0) {
-            const uint32_t ru = rr == 0 ? L - 1 : rr - 1, rd = rr == (uint32_t)L - 1 ? 0 : rr + 1;
-            p0 = rr | (ru << 8) | (rd << 16) | (cc << 24);
+            const uint64_t w = ((uint64_t)shfl32(rhi, rr) << 32) | shfl32(rlo, rr);
+            const uint64_t wu = ((uint64_t)shfl32(rhi, ru) << 32) | shfl32(rlo, ru);
+            const uint64_t wd = ((uint64_t)shfl32(rhi, rd) << 32) | shfl32(rlo, rd);
+            d = ising_d(w, wu, wd, cc, L);
+            pk = (uint32_t)(d + 4) | ((uint32_t)rr << 4) | ((uint32_t)cc << 10);
         } else {
-            p0 = rr | (cc << 8) | ((uint32_t)(((uint64_t)x.y * qm1) >> 32) << 16);
+            const uint32_t s0 = llat[site];
+            const uint32_t n0 = llat[s_up], n1 = llat[s_dn], n2 = llat[s_lf], n3 = llat[s_rt];
+            const uint32_t off = (uint32_t)(((uint64_t)x.y * qm1) >> 32);
+            uint32_t nv = s0 + 1u + off;
+            nv = nv >= q ? nv - q : nv;
+            const int nold = (n0 == s0) + (n1 == s0) + (n2 == s0) + (n3 == s0);
+            const int nnew = (n0 == nv) + (n1 == nv) + (n2 == nv) + (n3 == nv);
+            d = nold - nnew;
+            // d + 4 | new state | site | proposal offset (sites < 4096, q <= 255)
+            pk = (uint32_t)(d + 4) | (nv << 4) | ((uint32_t)site << 12) | (off << 24);
         }
         const double vbl = threshold_of(u53_of(x));
-        const int n = (int)((X - j0) < 64 ? (X - j0) : 64);
-        for (int i = 0; i < n; ++i) {
-            const uint32_t pk = rl(p0, i);
-            const double vb = rld(vbl, i);
-            // candidate outcomes, all lanes at once (pads give +inf -> reject)
-            const int nbl = b + cand;
-            const double lngn = __builtin_fma((double)lH[nbl], scale, lbase[nbl]);
-            const double dl = lngc - lngn;
-            // the move itself (wave-uniform): bin change d
-            int d, wsite = 0, rrow = 0;
-            uint32_t pnew = 0, nlo = 0, nhi = 0;
-            if (MODEL == 0) {
-                rrow = pk & 0xff;
-                const int ru = (pk >> 8) & 0xff, rd = (pk >> 16) & 0xff, col = pk >> 24;
-                const int cl = col == 0 ? L - 1 : col - 1, cr = col == L - 1 ? 0 : col + 1;
-                const uint64_t w = ((uint64_t)rl(rhi, rrow) << 32) | rl(rlo, rrow);
-                const uint64_t wu = ((uint64_t)rl(rhi, ru) << 32) | rl(rlo, ru);
-                const uint64_t wd = ((uint64_t)rl(rhi, rd) << 32) | rl(rlo, rd);
-                const uint32_t sp = (uint32_t)(w >> col) & 1u;
-                const uint32_t ones = ((uint32_t)(wu >> col) & 1u) + ((uint32_t)(wd >> col) & 1u) +
-                                      ((uint32_t)(w >> cl) & 1u) + ((uint32_t)(w >> cr) & 1u);
-                d = (sp ? (int)ones : 4 - (int)ones) - 2;
-                const uint64_t wn = w ^ (1ull << col);
-                nlo = (uint32_t)wn;
-                nhi = (uint32_t)(wn >> 32);
-            } else {
-                const int r0 = pk & 0xff, c0 = (pk >> 8) & 0xff;
-                wsite = r0 * L + c0;
-                const int up = r0 == 0 ? wsite + N - L : wsite - L;
-                const int dn = r0 == L - 1 ? wsite - N + L : wsite + L;
-                const int lf = c0 == 0 ? wsite + L - 1 : wsite - 1;
-                const int rt = c0 == L - 1 ? wsite - L + 1 : wsite + 1;
-                const int s0 = llat[wsite];
-                const int n0 = llat[up], n1 = llat[dn], n2 = llat[lf], n3 = llat[rt];
-                uint32_t nv = (uint32_t)s0 + 1u + (pk >> 16);
-                nv = nv >= q ? nv - q : nv;
-                pnew = nv;
-                const int nold = (n0 == s0) + (n1 == s0) + (n2 == s0) + (n3 == s0);
-                const int nnew = (n0 == (int)nv) + (n1 == (int)nv) + (n2 == (int)nv) + (n3 == (int)nv);
-                d = __builtin_amdgcn_readfirstlane(nold - nnew);
-                pnew = (uint32_t)__builtin_amdgcn_readfirstlane((int)pnew);
+        // later attempts of the chunk whose neighbourhood holds this attempt's site
+        if (lane < n) atomicOr((unsigned long long*)&lmap[site], 1ull << lane);
+        uint64_t aff = lmap[site] | lmap[s_up] | lmap[s_dn] | lmap[s_lf] | lmap[s_rt];
+        aff &= lane == 63 ? 0ull : (~0ull << (lane + 1));
+        if (lane < n) lmap[site] = 0;
+        uint64_t stale = 0;               // attempts whose precomputed d may be out of date
+
+        // ---- the chain
+        uint64_t ibit = 1;                // 1 << i
+        for (int i = 0; i < n; ++i, ibit <<= 1) {
+            const uint32_t pki = rl(pk, i);
+            int di = (int)(pki & 15u) - 4;
+            uint32_t nvi = (pki >> 4) & 255u;     // Potts: the proposed state
+            if (__builtin_expect((stale & ibit) != 0, 0)) {
+                if (MODEL == 0) {
+                    const int r0 = (pki >> 4) & 63, c0 = pki >> 10;
+                    const int r_u = r0 == 0 ? L - 1 : r0 - 1, r_d = r0 == L - 1 ? 0 : r0 + 1;
+                    const uint64_t w = ((uint64_t)rl(rhi, r0) << 32) | rl(rlo, r0);
+                    const uint64_t wu = ((uint64_t)rl(rhi, r_u) << 32) | rl(rlo, r_u);
+                    const uint64_t wd = ((uint64_t)rl(rhi, r_d) << 32) | rl(rlo, r_d);
+                    di = ising_d(w, wu, wd, c0, L);
+                } else {
+                    const int ws = (int)((pki >> 12) & 4095u);
+                    const int r0 = ws / L, c0 = ws - r0 * L;
+                    const int up = r0 == 0 ? ws + N - L : ws - L;
+                    const int dn = r0 == L - 1 ? ws - N + L : ws + L;
+                    const int lf = c0 == 0 ? ws + L - 1 : ws - 1;
+                    const int rt = c0 == L - 1 ? ws - L + 1 : ws + 1;
+                    const int s0 = llat[ws];
+                    const int n0 = llat[up], n1 = llat[dn], n2 = llat[lf], n3 = llat[rt];
+                    int nv = s0 + 1 + (int)(pki >> 24);
+                    nv = nv >= (int)q ? nv - (int)q : nv;
+                    const int nold = (n0 == s0) + (n1 == s0) + (n2 == s0) + (n3 == s0);
+                    const int nnew = (n0 == nv) + (n1 == nv) + (n2 == nv) + (n3 == nv);
+                    di = __builtin_amdgcn_readfirstlane(nold - nnew);
+                    nvi = (uint32_t)__builtin_amdgcn_readfirstlane(nv);
+                }
             }
-            // fast decisions of all candidates as lane masks; pick candidate d.
-            // dl - vb > 0 <=> dl > vb exactly (IEEE subtraction keeps the sign)
-            const double e = dl - vb;
+            const double vb = rld(vbl, i);
+            const int pos = idx + di;
+            // every candidate bin at once; dl - vb > 0 <=> dl > vb exactly, and an
+            // accept so decided is final; a reject inside the band is re-decided
+            const double e = (lngc - gl) - vb;
             const uint64_t acc = __ballot(e > 0.0);
-            const uint64_t und = __ballot(e >= -2.0 * kBand) & ~acc;
-            int f = (int)((acc >> (d + 4)) & 1u);
-            if (__builtin_expect((und >> (d + 4)) & 1u, 0)) {
-                const double delta = rld(dl, d + 4);
+            const uint64_t band = __ballot(e >= -2.0 * kBand);   // holds acc
+            const uint64_t sel = 1ull << pos;
+            int f = (acc & sel) != 0;
+            if (__builtin_expect(((band & ~acc) & sel) != 0, 0)) {
+                const double delta = rld(lngc - gl, pos);
                 f = __builtin_amdgcn_readfirstlane(
-                    slow_decide(I, T0 + (uint64_t)(j0 + i), (uint32_t)slot, delta) ? 1 : 0);
+                    slow_decide(I, T0 + (uint64_t)j0 + (uint64_t)i, (uint32_t)slot, delta) ? 1 : 0);
             }
             if (f) {
-                lngc = rld(lngn, d + 4);
-                b += d;
+                idx = pos;
+                lngc = rld(gl, pos);
+                stale |= rl64(aff, i);
                 if (MODEL == 0) {
-                    if (lane == rrow) {
-                        rlo = nlo;
-                        rhi = nhi;
+                    const int r0 = (pki >> 4) & 63, c0 = pki >> 10;
+                    const uint64_t m = 1ull << c0;
+                    if (lane == r0) {
+                        rlo ^= (uint32_t)m;
+                        rhi ^= (uint32_t)(m >> 32);
                     }
                 } else {
-                    if (lane == 0) llat[wsite] = (uint8_t)pnew;
+                    if (lane == 0) llat[(pki >> 12) & 4095u] = (uint8_t)nvi;
                 }
             }
             lngc += incv;
-            if (lane == 0) atomicAdd(&lH[b], inc);          // LDS add, no return value
+            if (lane == idx) gl += incv;
+            if (__builtin_expect(idx < 4 || idx > 59, 0)) {
+                store_window();
+                const int bb = b0 + idx;
+                b0 = bb - 32 < 0 ? 0 : (bb - 32 > b0max ? b0max : bb - 32);
+                idx = bb - b0;
+                load_window();
+            }
         }
     }
+    store_window();
     row = ((uint64_t)rhi << 32) | rlo;
 
     // ---- write back
@@ -493,7 +570,7 @@ __device__ void sweep_wave(const Inst& I, const Tile& tile, char* smem)
         for (int i = lane; i < N; i += 64) I.plat[(size_t)slot * N + i] = llat[i];
     }
     if (lane == 0) {
-        I.bin[slot] = b - kPad + lo;
+        I.bin[slot] = b0 + idx - kPad + lo;
         I.swaps[slot] = -1;
     }
     // ---- flatness (Sec. II.A): wave-wide min and sum of the walker's counts
