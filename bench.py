@@ -18,6 +18,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -152,6 +154,54 @@ def converge(rw, kw: dict, label: str, tune, max_s: float, seed: int) -> dict:
     return out
 
 
+def warm_start_study(rw, args) -> dict:
+    """Time to converge with the network's warm start (ln f from 2^-k0) against
+    plain flat-start REWL on the same targets: the network is trained on REWL's
+    own results for smaller systems, produced in the same run."""
+    from paper_1407_5140_amd import warm as Wm
+    types = [("ising", 2, 16), ("ising", 2, 24), ("ising", 2, 32), ("potts", 4, 16), ("potts", 4, 24),
+             ("potts", 8, 16), ("potts", 8, 24), ("potts", 10, 16), ("potts", 10, 24)]
+    log = lambda m: print(f"[warm] {m}", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    kws = Wm.training_workload(types, m=32, kfinal=args.train_kfinal)
+    g, res = Wm.run_to_convergence(kws, args.max_seconds, log=log)
+    ok = [r["converged"] for r in res]
+    x, t = Wm.training_rows(g, kws, ok)
+    g.close()
+    t_train = time.perf_counter() - t0
+    log(f"training set: {sum(ok)}/{len(kws)} instances converged to 2^-{args.train_kfinal}, "
+        f"{len(t)} rows, {t_train:.1f} s")
+    net, info = Wm.train(x, t, steps=args.mlp_steps, batch=4096, lr=1e-3)
+    log(f"network: {info}")
+    targets = [dict(model="potts", q=10, L=32, n_windows=16, m=32, kfinal=args.kfinal, X=10000, seed=1),
+               dict(model="ising", q=2, L=48, n_windows=32, m=32, kfinal=args.kfinal, X=10000, seed=1)]
+    out = []
+    for kw in targets:
+        label = f"{kw['model']} q={kw['q']} L={kw['L']} h={kw['n_windows']} m={kw['m']}"
+        tab = Wm.warm_table(net, kw)
+        row = {"workload": label, "kfinal": kw["kfinal"], "k0_warm": args.k0}
+        ex = exact_ln_g(kw)
+        for mode in ("warm", "plain"):
+            k = dict(kw, k0=args.k0 if mode == "warm" else 0)
+            gg, rr = Wm.run_to_convergence([k], args.target_seconds,
+                                           warm_tables=[tab] if mode == "warm" else None, log=log)
+            r = dict(rr[0])
+            if ex is not None and r["converged"]:
+                lng, _ = gg.concat(0)
+                okb = np.isfinite(ex)
+                r["eps_max"] = float(np.max(np.abs(lng[okb] - ex[okb]) / np.abs(ex[okb])))
+            gg.close()
+            row[mode] = r
+            log(f"{label} {mode}: {r}")
+        if row["warm"]["converged"] and row["plain"]["converged"]:
+            row["speedup"] = row["plain"]["seconds"] / row["warm"]["seconds"]
+        out.append(row)
+    net.close()
+    return {"mode": "warm-start vs plain REWL", "train": {"instances": len(kws), "kfinal": args.train_kfinal,
+            "converged": int(sum(ok)), "rows": int(len(t)), "seconds": t_train},
+            "network": info, "targets": out}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -170,6 +220,14 @@ def main(argv=None):
                     help="only copy a device buffer of this size and exit (a kernel of known "
                          "traffic for scaling the HBM byte counters)")
     ap.add_argument("--wpb", type=int, default=0, help="walkers per block (0 = library choice)")
+    ap.add_argument("--warm", action="store_true",
+                    help="train the DOS network on REWL results of small systems and compare "
+                         "time to converge, warm start against plain REWL, on larger targets")
+    ap.add_argument("--train-kfinal", type=int, default=16)
+    ap.add_argument("--kfinal", type=int, default=18, help="--warm: targets' final ln f = 2^-kfinal")
+    ap.add_argument("--k0", type=int, default=10, help="--warm: warm start's initial ln f = 2^-k0")
+    ap.add_argument("--mlp-steps", type=int, default=4000)
+    ap.add_argument("--target-seconds", type=float, default=200.0)
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is "
@@ -189,6 +247,9 @@ def main(argv=None):
         print(f"[bench] calibration copy of {args.calib_copy_mib} MiB done", file=sys.stderr, flush=True)
         return 0
 
+    if args.warm:
+        print(json.dumps(warm_start_study(rw, args)), flush=True)
+        return 0
     kws = workload(args.workload)
     label = LABELS[args.workload]
     if args.converge:

@@ -38,9 +38,9 @@ extern "C" {
 
 typedef struct {
     int32_t in_dim;     /* inputs per row, 1..16 (3 for the (E/N, 1/L, q) encoding)        */
-    int32_t hidden;     /* units per hidden layer: a multiple of 32, 32..4096              */
+    int32_t hidden;     /* units per hidden layer: a multiple of 64, 64..4096              */
     int32_t layers;     /* hidden layers, 1..16                                            */
-    int32_t max_batch;  /* largest batch a call may use (rounded up to a multiple of 32)   */
+    int32_t max_batch;  /* largest batch a call may use, 1..2^20 (rounded up to a multiple of 64) */
     uint64_t seed;      /* initial weights: uniform in +-1/sqrt(fan_in), biases zero       */
 } mlp_config;
 
@@ -69,7 +69,7 @@ rewl_status mlp_infer(mlp_handle* h, const float* x, float* y, int32_t B);
 rewl_status mlp_grad(mlp_handle* h, const float* x, const float* t, int32_t B, float* grad,
                      float* loss);
 
-/* `steps` Adam steps with learning rate lr, each on B rows (a multiple of 32,
+/* `steps` Adam steps with learning rate lr, each on B rows (a multiple of 64,
  * <= max_batch) drawn with replacement from the n host rows x[n][in_dim], t[n]
  * (1 <= n < 2^31, uploaded once per call) by a hash of (seed, handle's step
  * count).  *last_loss (may be NULL) receives the last step's batch loss. */
@@ -84,8 +84,8 @@ rewl_status mlp_fit(mlp_handle* h, const float* x, const float* t, int64_t n, in
 rewl_status mlp_warm_table(mlp_handle* h, int32_t model, int32_t q, int32_t L, double* lng_host);
 
 /* Diagnostic: C = A B on the matrix cores with BF16-rounded operands and FP32
- * accumulation; host arrays, A[M][K], B[K][N], C[M][N]; M, N multiples of 32,
- * K a multiple of 16. */
+ * accumulation; host arrays, A[M][K], B[K][N], C[M][N]; M, N multiples of 64,
+ * K a multiple of 32. */
 rewl_status mlp_probe_gemm(const float* A, const float* B, int32_t M, int32_t N, int32_t K, float* C);
 
 #ifdef __cplusplus

@@ -49,46 +49,83 @@ __device__ __forceinline__ float gelu_grad(float a)
 }
 
 // ---------------------------------------------------------------- GEMM
-// C[M][N] = sum_k A(i,k) B(k,j) with A(i,k) = A[i*lda + k] (or A[k*lda + i] if
-// ta) and B(k,j) = B[k*ldb + j] (or B[j*ldb + k] if tb); BF16 inputs, FP32
-// accumulation.  One wave per 32 x 32 output tile; M, N multiples of 32, K of 16.
-// Operand layout of v_mfma_f32_32x32x16_bf16: lane l supplies A rows i = l%32,
-// k = 8*(l/32) .. +7 and B columns j = l%32, same k; the 16 accumulators of lane
-// l hold C(8*(r/4) + 4*(l/32) + r%4, l%32), r = 0..15.
+// C = op(A) op(B) on the matrix cores: A(i,k) = A[i*lda + k] (ta = 0) or
+// A[k*lda + i] (ta = 1); B(k,j) = B[k*ldb + j] (tb = 0) or B[j*ldb + k] (tb = 1);
+// BF16 operands, FP32 accumulation.  A block of 4 waves computes a 64 x 64 tile
+// of C, one 32 x 32 quarter per wave, with K staged through LDS 32 at a time:
+// A as [i][k] and B as [j][k], so that each lane's 8 consecutive k are one
+// 16-byte read.  M and N are multiples of 64, K / gridDim.z a multiple of 32.
+// With gridDim.z > 1 (split K; plain stores only) split z writes its FP32 partial
+// product to C + z*M*N and k_splitk_sum adds the splits in order.
+// Operand layout of v_mfma_f32_32x32x16_bf16: lane l supplies A row l%32 and B
+// column l%32 with k = 8*(l/32) .. +7; its 16 accumulators hold
+// C(8*(r/4) + 4*(l/32) + r%4, l%32), r = 0..15.
 enum Epi : int {
     kEpiStore = 0,        // C = acc (FP32)
     kEpiBiasGelu = 1,     // pre = acc + bias[j] (FP32 out), act = gelu(pre) (BF16 out)
     kEpiGeluGrad = 2,     // d = acc * gelu'(pre) (FP32 and BF16 out)
 };
+constexpr int kBM = 64, kBN = 64, kBK = 32, kLdsRow = kBK + 8;   // +8: spread the banks
 
-__global__ void __launch_bounds__(64) k_gemm(const __bf16* __restrict__ A, int lda, int ta,
-                                             const __bf16* __restrict__ B, int ldb, int tb,
-                                             int M, int N, int K, int epi,
-                                             float* __restrict__ C, int ldc,
-                                             const float* __restrict__ bias,
-                                             const float* __restrict__ pre,
-                                             __bf16* __restrict__ out16)
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(256) k_gemm(const __bf16* __restrict__ A, int lda, int ta,
+                                              const __bf16* __restrict__ B, int ldb, int tb,
+                                              int M, int N, int K, int epi,
+                                              float* __restrict__ C, int ldc,
+                                              const float* __restrict__ bias,
+                                              const float* __restrict__ pre,
+                                              __bf16* __restrict__ out16)
 {
-    const int lane = threadIdx.x;
-    const int i0 = blockIdx.y * 32, j0 = blockIdx.x * 32;
+    __shared__ __align__(16) __bf16 As[kBM * kLdsRow];
+    __shared__ __align__(16) __bf16 Bs[kBN * kLdsRow];
+    const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+    const int i0 = blockIdx.y * kBM, j0 = blockIdx.x * kBN;
+    const int kspan = K / (int)gridDim.z, kbeg = (int)blockIdx.z * kspan, kend = kbeg + kspan;
+    const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;
     const int li = lane & 31, kg = (lane >> 5) * 8;
     f32x16 acc = {};
-    for (int k0 = 0; k0 < K; k0 += 16) {
-        bf16x8 av, bv;
+    for (int k0 = kbeg; k0 < kend; k0 += kBK) {
+        // stage: every thread moves 8 consecutive elements of A and of B
+        if (ta == 0) {
+            const int r = t >> 2, c = (t & 3) * 8;
+            *(u32x4*)&As[r * kLdsRow + c] = *(const u32x4*)&A[(size_t)(i0 + r) * lda + k0 + c];
+        } else {
+            const int kk = t >> 3, c = (t & 7) * 8;
+            u32x4 v = *(const u32x4*)&A[(size_t)(k0 + kk) * lda + i0 + c];
+            const __bf16* e = (const __bf16*)&v;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int k = k0 + kg + u;
-            av[u] = ta ? A[(size_t)k * lda + i0 + li] : A[(size_t)(i0 + li) * lda + k];
-            bv[u] = tb ? B[(size_t)(j0 + li) * ldb + k] : B[(size_t)k * ldb + j0 + li];
+            for (int u = 0; u < 8; ++u) As[(c + u) * kLdsRow + kk] = e[u];
         }
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
+        if (tb == 1) {
+            const int r = t >> 2, c = (t & 3) * 8;
+            *(u32x4*)&Bs[r * kLdsRow + c] = *(const u32x4*)&B[(size_t)(j0 + r) * ldb + k0 + c];
+        } else {
+            const int kk = t >> 3, c = (t & 7) * 8;
+            u32x4 v = *(const u32x4*)&B[(size_t)(k0 + kk) * ldb + j0 + c];
+            const __bf16* e = (const __bf16*)&v;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) Bs[(c + u) * kLdsRow + kk] = e[u];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < kBK; ks += 16) {
+            const bf16x8 av = *(const bf16x8*)&As[(wi + li) * kLdsRow + ks + kg];
+            const bf16x8 bv = *(const bf16x8*)&Bs[(wj + li) * kLdsRow + ks + kg];
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
+        }
+        __syncthreads();
     }
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-        const int i = i0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        const int j = j0 + li;
-        const size_t o = (size_t)i * ldc + j;
+        const int i = i0 + wi + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int j = j0 + wj + li;
         const float v = acc[r];
+        if (gridDim.z > 1) {
+            C[(size_t)blockIdx.z * M * N + (size_t)i * N + j] = v;
+            continue;
+        }
+        const size_t o = (size_t)i * ldc + j;
         if (epi == kEpiStore) {
             C[o] = v;
         } else if (epi == kEpiBiasGelu) {
@@ -101,6 +138,57 @@ __global__ void __launch_bounds__(64) k_gemm(const __bf16* __restrict__ A, int l
             out16[o] = (__bf16)d;
         }
     }
+}
+
+// out[e] = sum over splits z (in order) of part[z*n + e]
+__global__ void k_splitk_sum(const float* __restrict__ part, int S, int n, float* __restrict__ out)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    float s = 0.f;
+    for (int z = 0; z < S; ++z) s += part[(size_t)z * n + e];
+    out[e] = s;
+}
+
+// Weighted column sums over the batch, in two passes with a fixed order:
+// part[z][k][j] = sum over rows r of chunk z of w_k(r) Mx[r][j], where w_k(r) =
+// W[r*ldw + k] for k < nw and 1 for k = nw when `ones`; then k_colsum_final adds
+// the chunks.  Gradients of the output layer, of the biases and of the first layer.
+constexpr int kColK = 17;   // nw + ones <= in_dim + 1 <= 17
+template <class T>
+__global__ void k_colsum_part(const T* __restrict__ Mx, int ldm, int Bn, int H,
+                              const float* __restrict__ W, int ldw, int nw, int ones, int rows,
+                              float* __restrict__ part)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x, z = blockIdx.y;
+    if (j >= H) return;
+    const int K = nw + ones, r0 = z * rows, r1 = r0 + rows < Bn ? r0 + rows : Bn;
+    float acc[kColK];
+#pragma unroll
+    for (int k = 0; k < kColK; ++k) acc[k] = 0.f;
+    for (int r = r0; r < r1; ++r) {
+        const float v = (float)Mx[(size_t)r * ldm + j];
+#pragma unroll
+        for (int k = 0; k < kColK; ++k)
+            if (k < nw) acc[k] += W[(size_t)r * ldw + k] * v;
+        if (ones) {
+#pragma unroll
+            for (int k = 0; k < kColK; ++k)
+                if (k == nw) acc[k] += v;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kColK; ++k)
+        if (k < K) part[((size_t)z * K + k) * H + j] = acc[k];
+}
+
+__global__ void k_colsum_final(const float* __restrict__ part, int Z, int KH, float* __restrict__ out)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= KH) return;
+    float s = 0.f;
+    for (int z = 0; z < Z; ++z) s += part[(size_t)z * KH + e];
+    out[e] = s;
 }
 
 // first layer: pre = x W1 + b1 (K = in_dim), act = gelu(pre) in BF16
@@ -117,15 +205,18 @@ __global__ void k_layer_in(const float* __restrict__ x, int in_dim, const float*
     act[idx] = (__bf16)gelu(s);
 }
 
-// output layer y = act . w + b0 (FP32), one thread per row
-__global__ void k_layer_out(const __bf16* __restrict__ act, const float* __restrict__ w,
-                            const float* __restrict__ b0, int H, int B, float* __restrict__ y)
+// output layer y = act . w + b0 (FP32), one wave per row, fixed reduction order
+__global__ void __launch_bounds__(256) k_layer_out(const __bf16* __restrict__ act,
+                                                   const float* __restrict__ w,
+                                                   const float* __restrict__ b0, int H, int B,
+                                                   float* __restrict__ y)
 {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= B) return;
-    float s = b0[0];
-    for (int j = 0; j < H; ++j) s += (float)act[(size_t)r * H + j] * w[j];
-    y[r] = s;
+    const int row = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (row >= B) return;
+    float s = 0.f;
+    for (int j = lane; j < H; j += 64) s += (float)act[(size_t)row * H + j] * w[j];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if (lane == 0) y[row] = s + b0[0];
 }
 
 // loss pieces: dy = 2 (y - t) / B for rows < nvalid, 0 for padding; loss sum
@@ -154,44 +245,6 @@ __global__ void k_back_out(const float* __restrict__ dy, const float* __restrict
     const float d = dy[r] * w[j] * gelu_grad(pre[idx]);
     dpre[idx] = d;
     dpre16[idx] = (__bf16)d;
-}
-
-// column sums over the batch: out[j] = sum_r M[r][j] (and optionally weighted by v[r] x act)
-__global__ void k_colsum(const float* __restrict__ Mx, int H, int B, float* __restrict__ out)
-{
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= H) return;
-    float s = 0.f;
-    for (int r = 0; r < B; ++r) s += Mx[(size_t)r * H + j];
-    out[j] = s;
-}
-
-// grad of w_out: g[j] = sum_r dy[r] act[r][j]; grad of b_out = sum dy
-__global__ void k_grad_out(const float* __restrict__ dy, const __bf16* __restrict__ act, int H,
-                           int B, float* __restrict__ gw, float* __restrict__ gb)
-{
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j > H) return;
-    float s = 0.f;
-    if (j == H) {
-        for (int r = 0; r < B; ++r) s += dy[r];
-        gb[0] = s;
-        return;
-    }
-    for (int r = 0; r < B; ++r) s += dy[r] * (float)act[(size_t)r * H + j];
-    gw[j] = s;
-}
-
-// grad of W1: g[i][j] = sum_r x[r][i] d[r][j]
-__global__ void k_grad_in(const float* __restrict__ x, int in_dim, const float* __restrict__ d,
-                          int H, int B, float* __restrict__ g)
-{
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= in_dim * H) return;
-    const int i = idx / H, j = idx - i * H;
-    float s = 0.f;
-    for (int r = 0; r < B; ++r) s += x[r * in_dim + i] * d[(size_t)r * H + j];
-    g[idx] = s;
 }
 
 // Adam (Kingma & Ba) on the FP32 master weights, BF16 copies refreshed
@@ -253,6 +306,10 @@ struct mlp_handle {
     float *dpre = nullptr, *dtmp = nullptr, *y = nullptr, *dy = nullptr, *loss = nullptr;
     __bf16 *d16a = nullptr, *d16b = nullptr;
     float *xb = nullptr, *yb = nullptr;
+    float* kpart = nullptr;            // split-K partial products [Smax][H][H]
+    int Smax = 1;
+    float* cpart = nullptr;            // column-sum partials [Zmax][kColK][H]
+    int crow = 64;                     // rows per column-sum chunk
     float *dx = nullptr, *dt = nullptr;   // training rows of the last mlp_fit call
     int64_t data_cap = 0;
     int64_t steps = 0;
@@ -273,17 +330,40 @@ namespace {
 
 inline dim3 grid1(int n, int b = 256) { return dim3((n + b - 1) / b); }
 
-// forward pass of B rows (B a multiple of 32) already in xb; y written
+// C = op(A) op(B) with the handle's split-K buffer when K is long
+void gemm(mlp_handle* h, const __bf16* A, int lda, int ta, const __bf16* B, int ldb, int tb, int M, int N,
+          int K, int epi, float* C, int ldc, const float* bias, const float* pre, __bf16* out16)
+{
+    int S = 1;
+    if (epi == kEpiStore && M * N <= h->H * h->H)
+        while (S < h->Smax && K % (2 * S * kBK) == 0 && K / (2 * S) >= 256) S *= 2;
+    hipLaunchKernelGGL(k_gemm, dim3(N / kBN, M / kBM, S), dim3(256), 0, h->stream, A, lda, ta, B, ldb, tb,
+                       M, N, K, epi, S > 1 ? h->kpart : C, ldc, bias, pre, out16);
+    if (S > 1)
+        hipLaunchKernelGGL(k_splitk_sum, grid1(M * N), dim3(256), 0, h->stream, h->kpart, S, M * N, C);
+}
+
+// out[k][j] = sum_r w_k(r) Mx[r][j] over B rows (see k_colsum_part)
+template <class T>
+void colsum(mlp_handle* h, const T* Mx, int ldm, int B, int H, const float* W, int ldw, int nw, int ones,
+            float* out)
+{
+    const int Z = (B + h->crow - 1) / h->crow, K = nw + ones;
+    hipLaunchKernelGGL(k_colsum_part<T>, dim3((H + 63) / 64, Z), dim3(64), 0, h->stream, Mx, ldm, B, H, W, ldw,
+                       nw, ones, h->crow, h->cpart);
+    hipLaunchKernelGGL(k_colsum_final, grid1(K * H), dim3(256), 0, h->stream, h->cpart, Z, K * H, out);
+}
+
+// forward pass of B rows (B a multiple of 64) already in xb; y written
 void forward(mlp_handle* h, const float* x, int B)
 {
     const int H = h->H;
     hipLaunchKernelGGL(k_layer_in, grid1(B * H), dim3(256), 0, h->stream, x, h->cfg.in_dim,
                        h->p + h->off_W[0], h->p + h->off_b[0], H, B, h->pre[0], h->act[0]);
     for (int l = 1; l < h->nl; ++l)
-        hipLaunchKernelGGL(k_gemm, dim3(H / 32, B / 32), dim3(64), 0, h->stream, h->act[l - 1], H, 0,
-                           h->p16 + h->off16[l], H, 0, B, H, H, (int)kEpiBiasGelu, h->pre[l], H,
-                           h->p + h->off_b[l], (const float*)nullptr, h->act[l]);
-    hipLaunchKernelGGL(k_layer_out, grid1(B), dim3(256), 0, h->stream, h->act[h->nl - 1],
+        gemm(h, h->act[l - 1], H, 0, h->p16 + h->off16[l], H, 0, B, H, H, kEpiBiasGelu, h->pre[l], H,
+             h->p + h->off_b[l], nullptr, h->act[l]);
+    hipLaunchKernelGGL(k_layer_out, dim3((B + 3) / 4), dim3(256), 0, h->stream, h->act[h->nl - 1],
                        h->p + h->off_wout, h->p + h->off_bout, H, B, h->y);
 }
 
@@ -293,29 +373,26 @@ void backward(mlp_handle* h, const float* x, const float* t, int B, int nvalid)
     const int H = h->H, nl = h->nl;
     (void)hipMemsetAsync(h->loss, 0, sizeof(float), h->stream);
     hipLaunchKernelGGL(k_loss, grid1(B), dim3(256), 0, h->stream, h->y, t, B, nvalid, h->dy, h->loss);
-    hipLaunchKernelGGL(k_grad_out, grid1(H + 1), dim3(256), 0, h->stream, h->dy, h->act[nl - 1], H, B,
-                       h->g + h->off_wout, h->g + h->off_bout);
+    // output layer: w_out gradient = act^T dy, b_out gradient = sum dy
+    colsum(h, h->act[nl - 1], H, B, H, h->dy, 1, 1, 0, h->g + h->off_wout);
+    colsum(h, h->dy, 1, B, 1, (const float*)nullptr, 0, 0, 1, h->g + h->off_bout);
     hipLaunchKernelGGL(k_back_out, grid1(B * H), dim3(256), 0, h->stream, h->dy, h->p + h->off_wout,
                        h->pre[nl - 1], H, B, h->dpre, h->d16a);
     __bf16* dcur = h->d16a;
     __bf16* dnext = h->d16b;
     for (int l = nl - 1; l >= 1; --l) {
         // dW_l = act_{l-1}^T d_l  (K = B), db_l = column sums of d_l
-        hipLaunchKernelGGL(k_gemm, dim3(H / 32, H / 32), dim3(64), 0, h->stream, h->act[l - 1], H, 1,
-                           dcur, H, 0, H, H, B, (int)kEpiStore, h->g + h->off_W[l], H,
-                           (const float*)nullptr, (const float*)nullptr, (__bf16*)nullptr);
-        hipLaunchKernelGGL(k_colsum, grid1(H), dim3(256), 0, h->stream, h->dpre, H, B,
-                           h->g + h->off_b[l]);
+        gemm(h, h->act[l - 1], H, 1, dcur, H, 0, H, H, B, kEpiStore, h->g + h->off_W[l], H, nullptr, nullptr,
+             nullptr);
+        colsum(h, h->dpre, H, B, H, (const float*)nullptr, 0, 0, 1, h->g + h->off_b[l]);
         // d_{l-1} = (d_l W_l^T) * gelu'(pre_{l-1})
-        hipLaunchKernelGGL(k_gemm, dim3(H / 32, B / 32), dim3(64), 0, h->stream, dcur, H, 0,
-                           h->p16 + h->off16[l], H, 1, B, H, H, (int)kEpiGeluGrad, h->dtmp, H,
-                           (const float*)nullptr, h->pre[l - 1], dnext);
+        gemm(h, dcur, H, 0, h->p16 + h->off16[l], H, 1, B, H, H, kEpiGeluGrad, h->dtmp, H, nullptr,
+             h->pre[l - 1], dnext);
         std::swap(h->dpre, h->dtmp);
         std::swap(dcur, dnext);
     }
-    hipLaunchKernelGGL(k_grad_in, grid1(h->cfg.in_dim * H), dim3(256), 0, h->stream, x, h->cfg.in_dim,
-                       h->dpre, H, B, h->g + h->off_W[0]);
-    hipLaunchKernelGGL(k_colsum, grid1(H), dim3(256), 0, h->stream, h->dpre, H, B, h->g + h->off_b[0]);
+    // first layer: W1 gradient rows = x_i^T d_0, then b1 = column sums (contiguous in g)
+    colsum(h, h->dpre, H, B, H, x, h->cfg.in_dim, h->cfg.in_dim, 1, h->g + h->off_W[0]);
 }
 
 }  // namespace
@@ -339,14 +416,15 @@ rewl_status mlp_create(const mlp_config* c, void* hip_stream, mlp_handle** out)
 {
     if (!c || !out) return mfail(REWL_E_INVALID, "null argument");
     *out = nullptr;
-    if (c->in_dim < 1 || c->in_dim > 16 || c->hidden < 32 || c->hidden % 32 || c->hidden > 4096 ||
-        c->layers < 1 || c->layers > 16 || c->max_batch < 32 || c->max_batch > (1 << 20))
-        return mfail(REWL_E_INVALID, "need 1<=in_dim<=16, hidden a multiple of 32, 1<=layers<=16, max_batch>=32");
+    if (c->in_dim < 1 || c->in_dim > 16 || c->hidden < 64 || c->hidden % 64 || c->hidden > 4096 ||
+        c->layers < 1 || c->layers > 16 || c->max_batch < 1 || c->max_batch > (1 << 20))
+        return mfail(REWL_E_INVALID, "need 1<=in_dim<=16, hidden a multiple of 64 up to 4096, 1<=layers<=16, "
+                                     "1<=max_batch<=2^20");
     mlp_handle* h = new mlp_handle();
     h->cfg = *c;
     h->H = c->hidden;
     h->nl = c->layers;
-    h->Bmax = (c->max_batch + 31) / 32 * 32;
+    h->Bmax = (c->max_batch + 63) / 64 * 64;
     const int H = h->H;
     int off = 0;
     h->off_W.push_back(off);
@@ -399,6 +477,11 @@ rewl_status mlp_create(const mlp_config* c, void* hip_stream, mlp_handle** out)
     if (s == REWL_OK) s = h->alloc(&h->loss, 1);
     if (s == REWL_OK) s = h->alloc(&h->xb, (size_t)h->Bmax * c->in_dim);
     if (s == REWL_OK) s = h->alloc(&h->yb, h->Bmax);
+    // split-K partials: at most 16 splits and 64 MiB
+    while (h->Smax < 16 && (size_t)2 * h->Smax * H * H * 4 <= ((size_t)64 << 20)) h->Smax *= 2;
+    if (s == REWL_OK && h->Smax > 1) s = h->alloc(&h->kpart, (size_t)h->Smax * H * H);
+    h->crow = std::max(64, h->Bmax / 256);
+    if (s == REWL_OK) s = h->alloc(&h->cpart, (size_t)((h->Bmax + h->crow - 1) / h->crow) * kColK * H);
     if (s != REWL_OK) return bail(s);
     // initial weights: uniform(-1/sqrt(fan_in), 1/sqrt(fan_in)) from a fixed hash, biases 0
     std::vector<float> p0(h->P, 0.f);
@@ -464,7 +547,7 @@ rewl_status mlp_infer(mlp_handle* h, const float* x, float* y, int32_t B)
     const int in = h->cfg.in_dim;
     for (int r0 = 0; r0 < B; r0 += h->Bmax) {
         const int nb = std::min(h->Bmax, B - r0);
-        const int Bp = (nb + 31) / 32 * 32;
+        const int Bp = (nb + 63) / 64 * 64;
         MLP_TRY(hipMemsetAsync(h->xb, 0, (size_t)Bp * in * 4, h->stream));
         MLP_TRY(hipMemcpyAsync(h->xb, x + (size_t)r0 * in, (size_t)nb * in * 4, hipMemcpyHostToDevice, h->stream));
         forward(h, h->xb, Bp);
@@ -479,7 +562,7 @@ rewl_status mlp_infer(mlp_handle* h, const float* x, float* y, int32_t B)
 rewl_status mlp_grad(mlp_handle* h, const float* x, const float* t, int32_t B, float* grad_host, float* loss)
 {
     if (!h || !x || !t || B < 1 || B > h->Bmax) return mfail(REWL_E_INVALID, "need 1 <= B <= max_batch");
-    const int in = h->cfg.in_dim, Bp = (B + 31) / 32 * 32;
+    const int in = h->cfg.in_dim, Bp = (B + 63) / 64 * 64;
     MLP_TRY(hipMemsetAsync(h->xb, 0, (size_t)Bp * in * 4, h->stream));
     MLP_TRY(hipMemsetAsync(h->yb, 0, (size_t)Bp * 4, h->stream));
     MLP_TRY(hipMemcpyAsync(h->xb, x, (size_t)B * in * 4, hipMemcpyHostToDevice, h->stream));
@@ -498,8 +581,8 @@ rewl_status mlp_grad(mlp_handle* h, const float* x, const float* t, int32_t B, f
 rewl_status mlp_fit(mlp_handle* h, const float* x, const float* t, int64_t n, int32_t B, int64_t steps,
                     float lr, uint32_t seed, float* last_loss)
 {
-    if (!h || !x || !t || n < 1 || n > INT32_MAX || B < 32 || B > h->Bmax || B % 32 || steps < 0)
-        return mfail(REWL_E_INVALID, "need 1 <= n < 2^31 rows, B a multiple of 32 in [32, max_batch]");
+    if (!h || !x || !t || n < 1 || n > INT32_MAX || B < 64 || B > h->Bmax || B % 64 || steps < 0)
+        return mfail(REWL_E_INVALID, "need 1 <= n < 2^31 rows, B a multiple of 64 in [64, max_batch]");
     const int in = h->cfg.in_dim;
     if (n > h->data_cap) {
         if (h->dx) (void)hipFree(h->dx);
@@ -553,8 +636,8 @@ rewl_status mlp_warm_table(mlp_handle* h, int32_t model, int32_t q, int32_t L, d
 // Diagnostic: the BF16 MFMA GEMM on host data, C = A B (A: M x K, B: K x N).
 rewl_status mlp_probe_gemm(const float* A, const float* B, int32_t M, int32_t N, int32_t K, float* C)
 {
-    if (!A || !B || !C || M < 32 || N < 32 || K < 16 || M % 32 || N % 32 || K % 16)
-        return mfail(REWL_E_INVALID, "M, N multiples of 32, K of 16");
+    if (!A || !B || !C || M < 64 || N < 64 || K < 32 || M % 64 || N % 64 || K % 32)
+        return mfail(REWL_E_INVALID, "M, N multiples of 64, K of 32");
     std::vector<__bf16> a16((size_t)M * K), b16((size_t)K * N);
     for (size_t i = 0; i < a16.size(); ++i) a16[i] = (__bf16)A[i];
     for (size_t i = 0; i < b16.size(); ++i) b16[i] = (__bf16)B[i];
@@ -566,7 +649,7 @@ rewl_status mlp_probe_gemm(const float* A, const float* B, int32_t M, int32_t N,
     hipError_t e = hipMemcpy(da, a16.data(), a16.size() * 2, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(db, b16.data(), b16.size() * 2, hipMemcpyHostToDevice);
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_gemm, dim3(N / 32, M / 32), dim3(64), 0, 0, da, K, 0, db, N, 0, M, N, K,
+        hipLaunchKernelGGL(k_gemm, dim3(N / kBN, M / kBM, 1), dim3(256), 0, 0, da, K, 0, db, N, 0, M, N, K,
                            (int)kEpiStore, dc, N, (const float*)nullptr, (const float*)nullptr,
                            (__bf16*)nullptr);
         e = hipGetLastError();

@@ -380,17 +380,19 @@ static rewl_status create_impl(const rewl_config* cfgs, int32_t n, void* hip_str
         hi.nreach.assign(hi.h, 0);
         for (int a = 0; a < hi.h; ++a)
             for (int b = hi.lo[a]; b <= hi.hi[a]; ++b) hi.nreach[a] += hi.mask[b];
-        // sweep variant.  Both issue ~70 instructions per attempt step; the lane
-        // variant serves a whole wave of walkers with them, the wave variant one.
-        // With few walkers the chain latency, not the GPU's width, sets the rate
-        // and the two are on par for Ising (measured); the lane variant is chosen
-        // otherwise.
+        // sweep variant.  The lane variant serves a wave of walkers with ~70
+        // instructions per attempt; the wave variant serves one walker with ~34
+        // (chunked evaluation and runs).  With few walkers per SIMD the chain
+        // latency sets the rate and the wave variant wins (measured: Ising L=64
+        // 1024 walkers 1.39 vs 2.66 ms, Potts q=10 L=32 4096 walkers 1.78 vs
+        // 3.50 ms per 10^4 attempts); with tens of thousands of walkers the lane
+        // variant's width wins (the 64-instance batch).
         const bool wave_ok = c.model == 0 ? c.L <= 64 : hi.N <= kWaveMaxSites;
         int64_t total_walkers = 0;
         for (int u = 0; u < n; ++u) total_walkers += (int64_t)cfgs[u].n_windows * cfgs[u].walkers_per_window;
         hi.kind = REWL_SWEEP_LANE;
         if (wave_ok && (H->tune.sweep_kind == REWL_SWEEP_WAVE ||
-                        (H->tune.sweep_kind == REWL_SWEEP_AUTO && c.model == 0 && total_walkers <= 2048)))
+                        (H->tune.sweep_kind == REWL_SWEEP_AUTO && total_walkers <= 8192)))
             hi.kind = REWL_SWEEP_WAVE;
         if (hi.kind == REWL_SWEEP_LANE) {
             int want = H->tune.walkers_per_block > 0 ? H->tune.walkers_per_block : 64;
@@ -539,7 +541,8 @@ static rewl_status autotune(const rewl_config* cfgs, int32_t n, void* hip_stream
 {
     std::vector<rewl_tune> cand;
     bool all_wave = true;
-    for (int i = 0; i < n; ++i) all_wave = all_wave && (cfgs[i].model == 1 || cfgs[i].L <= 64);
+    for (int i = 0; i < n; ++i)
+        all_wave = all_wave && (cfgs[i].model == 0 ? cfgs[i].L <= 64 : cfgs[i].L * cfgs[i].L <= kWaveMaxSites);
     for (int kb : {40, 53, 80, 0}) {
         rewl_tune t = base;
         t.sweep_kind = REWL_SWEEP_LANE;

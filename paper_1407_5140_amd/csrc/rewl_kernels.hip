@@ -326,15 +326,15 @@ __global__ void __launch_bounds__(64) k_sweep(const Inst* __restrict__ insts,
 // LDS: base [nbins] shared by the block's walkers (all of one window), then per
 // wave its counts H [nbins], then (Potts) per wave its lattice [N].
 // LDS of the wave variant: the window's base table (shared), then per wave its
-// histogram, its site map (one 64-bit attempt mask per site) and, for Potts,
-// its lattice.
+// histogram, its site map (one 64-bit attempt mask per site) and its lattice
+// (Potts bytes, Ising one 64-bit word per row).
 __host__ __device__ inline size_t wave_lds_bytes(int model, int L, int WB, int G)
 {
     const size_t nb = (size_t)WB + 2 * kPad, N = (size_t)L * L;
     size_t s = nb * 8 + (size_t)G * nb * 4;
     s = (s + 7) & ~size_t(7);
     s += (size_t)G * N * 8;
-    if (model == 1) s += (size_t)G * N;
+    s += model == 1 ? (size_t)G * N : (size_t)G * L * 8;
     return s;
 }
 // the site map bounds the wave variant to lattices of at most 4096 sites
@@ -368,17 +368,19 @@ __device__ __forceinline__ int ising_d(uint64_t w, uint64_t wu, uint64_t wd, int
 }
 
 // Wave variant: one walker per wave.
-// * The walker's ln g and H over 64 consecutive bins live in registers, one bin
-//   per lane, so that the dependent chain of attempts touches no table memory:
-//   lane l holds bin b0 + l; the window is moved when the walker comes within
-//   four bins of its edge.
+// * The walker's ln g over 64 consecutive bins lives in registers, one bin per
+//   lane, so that no table memory is on the dependent chain; the window moves
+//   when the walker comes within four bins of its edge.
 // * Per chunk of 64 attempts the lanes draw the numbers and evaluate every
-//   attempt's bin change d on the lattice as it stands at the chunk start.  A
-//   per-site bit map in LDS gives each attempt the later attempts of the chunk
-//   whose site neighbourhood contains its site; an accepted move marks them,
-//   and a marked attempt re-evaluates d on the current lattice.
-// * The chain then only compares ln g differences (all candidate bins at once,
-//   one lane each) against the attempt's threshold.
+//   attempt's bin change d on the lattice.  A per-site bit map in LDS gives each
+//   attempt the earlier attempts of the chunk whose site lies in its
+//   neighbourhood (P); an attempt is out of date once one of those has flipped.
+// * The chain advances a run at a time.  From attempt i on, every lane j >= i
+//   evaluates its attempt as if the walker were still in its bin, with ln g
+//   raised by the (j - i) updates of the attempts in between: that holds while
+//   those attempts were rejected or were accepted with d = 0 (a move within the
+//   bin, always accepted).  The run ends at the first accepted move with d != 0,
+//   or before the first attempt that a flip of the run made out of date.
 template <int MODEL>
 __device__ void sweep_wave(const Inst& I, const Tile& tile, char* smem)
 {
@@ -398,7 +400,7 @@ __device__ void sweep_wave(const Inst& I, const Tile& tile, char* smem)
     const size_t off_map = ((size_t)nbins * 8 + (size_t)G * nbins * 4 + 7) & ~size_t(7);
     uint64_t* lmap = (uint64_t*)(smem + off_map) + (size_t)wave * N;
     uint8_t* llat = (uint8_t*)(smem + off_map + (size_t)G * N * 8) + (size_t)wave * N;
-    uint64_t row = 0;
+    uint64_t* lrow = (uint64_t*)(smem + off_map + (size_t)G * N * 8) + (size_t)wave * L;
     if (active) {
         for (int i = lane; i < nbins; i += 64) {
             const int b = i - kPad;
@@ -409,7 +411,7 @@ __device__ void sweep_wave(const Inst& I, const Tile& tile, char* smem)
         }
         for (int i = lane; i < N; i += 64) lmap[i] = 0;
         if (MODEL == 0) {
-            if (lane < L) row = I.lat[(size_t)slot * L + lane];
+            if (lane < L) lrow[lane] = I.lat[(size_t)slot * L + lane];
         } else {
             for (int i = lane; i < N; i += 64) llat[i] = I.plat[(size_t)slot * N + i];
         }
@@ -427,8 +429,9 @@ __device__ void sweep_wave(const Inst& I, const Tile& tile, char* smem)
     const int b = __builtin_amdgcn_readfirstlane(I.bin[slot] - lo + kPad);
 
     // register window of the walker's table: lane l holds ln g of bin b0 + l
-    // (+inf beyond the table); the counts are recovered from it when the window
-    // moves, H = (ln g - base) 2^k, exact like every value here
+    // (+inf beyond the table).  Every value is a multiple of 2^-(k + log2 m)
+    // below 2^21, so every step here is exact; the counts are recovered as
+    // H = (ln g - base) 2^k when the window moves.
     const int b0max = nbins > 64 ? nbins - 64 : 0;
     int b0 = b - 32 < 0 ? 0 : (b - 32 > b0max ? b0max : b - 32);
     int idx = b - b0;                     // the walker's bin, as a lane of the window
@@ -446,118 +449,108 @@ __device__ void sweep_wave(const Inst& I, const Tile& tile, char* smem)
     };
     load_window();
     double lngc = rld(gl, idx);          // ln g of the current bin (wave-uniform)
-    uint32_t rlo = (uint32_t)row, rhi = (uint32_t)(row >> 32);
+    const double laneinc = (double)lane * incv;
 
     for (int64_t j0 = 0; j0 < X; j0 += 64) {
         const int n = (int)((X - j0) < 64 ? (X - j0) : 64);
-        // ---- lanes: draws, sites and bin changes on the lattice at the chunk start
+        // ---- lanes: draws and sites of the chunk's attempts
         const u32x4 x = draw(I.k0, I.k1, T0 + (uint64_t)(j0 + lane), (uint32_t)slot, kTagFlip);
         const int site = (int)(((uint64_t)x.x * (uint32_t)N) >> 32);
         const int rr = site / L, cc = site - rr * L;
         const int ru = rr == 0 ? L - 1 : rr - 1, rd = rr == L - 1 ? 0 : rr + 1;
         const int cl = cc == 0 ? L - 1 : cc - 1, cr = cc == L - 1 ? 0 : cc + 1;
         const int s_up = ru * L + cc, s_dn = rd * L + cc, s_lf = rr * L + cl, s_rt = rr * L + cr;
-        int d;
-        uint32_t pk;
-        if (MODEL == 0) {
-            const uint64_t w = ((uint64_t)shfl32(rhi, rr) << 32) | shfl32(rlo, rr);
-            const uint64_t wu = ((uint64_t)shfl32(rhi, ru) << 32) | shfl32(rlo, ru);
-            const uint64_t wd = ((uint64_t)shfl32(rhi, rd) << 32) | shfl32(rlo, rd);
-            d = ising_d(w, wu, wd, cc, L);
-            pk = (uint32_t)(d + 4) | ((uint32_t)rr << 4) | ((uint32_t)cc << 10);
-        } else {
-            const uint32_t s0 = llat[site];
-            const uint32_t n0 = llat[s_up], n1 = llat[s_dn], n2 = llat[s_lf], n3 = llat[s_rt];
-            const uint32_t off = (uint32_t)(((uint64_t)x.y * qm1) >> 32);
-            uint32_t nv = s0 + 1u + off;
-            nv = nv >= q ? nv - q : nv;
-            const int nold = (n0 == s0) + (n1 == s0) + (n2 == s0) + (n3 == s0);
-            const int nnew = (n0 == nv) + (n1 == nv) + (n2 == nv) + (n3 == nv);
-            d = nold - nnew;
-            // d + 4 | new state | site | proposal offset (sites < 4096, q <= 255)
-            pk = (uint32_t)(d + 4) | (nv << 4) | ((uint32_t)site << 12) | (off << 24);
-        }
+        const uint32_t off = MODEL == 0 ? 0u : (uint32_t)(((uint64_t)x.y * qm1) >> 32);
+        int d;                            // bin change of this lane's attempt
+        uint32_t nv = 0;                  // Potts: proposed state
+        auto evaluate = [&]() {           // on the lattice as it stands
+            if (MODEL == 0) {
+                d = ising_d(lrow[rr], lrow[ru], lrow[rd], cc, L);
+            } else {
+                const uint32_t s0 = llat[site];
+                const uint32_t n0 = llat[s_up], n1 = llat[s_dn], n2 = llat[s_lf], n3 = llat[s_rt];
+                nv = s0 + 1u + off;
+                nv = nv >= q ? nv - q : nv;
+                const int nold = (n0 == s0) + (n1 == s0) + (n2 == s0) + (n3 == s0);
+                const int nnew = (n0 == nv) + (n1 == nv) + (n2 == nv) + (n3 == nv);
+                d = nold - nnew;
+            }
+        };
+        evaluate();
         const double vbl = threshold_of(u53_of(x));
-        // later attempts of the chunk whose neighbourhood holds this attempt's site
+        const double vbl2 = vbl - 2.0 * kBand;    // below it a reject is certain
+        // earlier attempts of the chunk whose site lies in this attempt's neighbourhood
         if (lane < n) atomicOr((unsigned long long*)&lmap[site], 1ull << lane);
-        uint64_t aff = lmap[site] | lmap[s_up] | lmap[s_dn] | lmap[s_lf] | lmap[s_rt];
-        aff &= lane == 63 ? 0ull : (~0ull << (lane + 1));
+        const uint64_t pm = (lmap[site] | lmap[s_up] | lmap[s_dn] | lmap[s_lf] | lmap[s_rt]) &
+                            ((1ull << lane) - 1);
         if (lane < n) lmap[site] = 0;
-        uint64_t stale = 0;               // attempts whose precomputed d may be out of date
+        const uint64_t live = n == 64 ? ~0ull : ((1ull << n) - 1);
+        uint64_t F = 0;                   // attempts flipped since the lanes last evaluated
 
-        // ---- the chain
-        uint64_t ibit = 1;                // 1 << i
-        for (int i = 0; i < n; ++i, ibit <<= 1) {
-            const uint32_t pki = rl(pk, i);
-            int di = (int)(pki & 15u) - 4;
-            uint32_t nvi = (pki >> 4) & 255u;     // Potts: the proposed state
-            if (__builtin_expect((stale & ibit) != 0, 0)) {
-                if (MODEL == 0) {
-                    const int r0 = (pki >> 4) & 63, c0 = pki >> 10;
-                    const int r_u = r0 == 0 ? L - 1 : r0 - 1, r_d = r0 == L - 1 ? 0 : r0 + 1;
-                    const uint64_t w = ((uint64_t)rl(rhi, r0) << 32) | rl(rlo, r0);
-                    const uint64_t wu = ((uint64_t)rl(rhi, r_u) << 32) | rl(rlo, r_u);
-                    const uint64_t wd = ((uint64_t)rl(rhi, r_d) << 32) | rl(rlo, r_d);
-                    di = ising_d(w, wu, wd, c0, L);
-                } else {
-                    const int ws = (int)((pki >> 12) & 4095u);
-                    const int r0 = ws / L, c0 = ws - r0 * L;
-                    const int up = r0 == 0 ? ws + N - L : ws - L;
-                    const int dn = r0 == L - 1 ? ws - N + L : ws + L;
-                    const int lf = c0 == 0 ? ws + L - 1 : ws - 1;
-                    const int rt = c0 == L - 1 ? ws - L + 1 : ws + 1;
-                    const int s0 = llat[ws];
-                    const int n0 = llat[up], n1 = llat[dn], n2 = llat[lf], n3 = llat[rt];
-                    int nv = s0 + 1 + (int)(pki >> 24);
-                    nv = nv >= (int)q ? nv - (int)q : nv;
-                    const int nold = (n0 == s0) + (n1 == s0) + (n2 == s0) + (n3 == s0);
-                    const int nnew = (n0 == nv) + (n1 == nv) + (n2 == nv) + (n3 == nv);
-                    di = __builtin_amdgcn_readfirstlane(nold - nnew);
-                    nvi = (uint32_t)__builtin_amdgcn_readfirstlane(nv);
+        int i = 0;
+        while (i < n) {
+            const uint64_t run = live & (~0ull << i);
+            if (F != 0 && (__builtin_amdgcn_ballot_w64((pm & F) != 0) & run) != 0) {
+                evaluate();
+                F = 0;
+            }
+            const int pos = idx + d;
+            const double gp = __builtin_bit_cast(
+                double, ((uint64_t)shfl32((uint32_t)(__builtin_bit_cast(uint64_t, gl) >> 32), pos) << 32) |
+                            shfl32((uint32_t)__builtin_bit_cast(uint64_t, gl), pos));
+            // ln g now - ln g of the candidate bin, exact
+            const double dl = (lngc - gp) + (laneinc - (double)i * incv);
+            const uint64_t zall = __builtin_amdgcn_ballot_w64(d == 0);
+            const uint64_t gt = __builtin_amdgcn_ballot_w64(dl > vbl);
+            const uint64_t ge = __builtin_amdgcn_ballot_w64(dl >= vbl2);     // holds gt
+            const uint64_t zero = zall & run;
+            const uint64_t acc = gt & ~zall & run;
+            uint64_t amb = ge & ~gt & ~zall & run;
+            const uint64_t hit = __builtin_amdgcn_ballot_w64((pm & zero) != 0) & run;
+            // an attempt both accepted and out of date is out of date: re-evaluated first
+            const uint64_t stop = acc | hit;
+            int js = stop ? (int)__builtin_ctzll(stop) : n;
+            bool move = ((acc & ~hit) >> js) & 1u;
+            // an attempt inside the guard band is decided exactly, in order
+            while (__builtin_expect((amb & (js >= 64 ? ~0ull : ((1ull << js) - 1))) != 0, 0)) {
+                const int kk = (int)__builtin_ctzll(amb);
+                amb &= amb - 1;
+                if (__builtin_amdgcn_readfirstlane(
+                        slow_decide(I, T0 + (uint64_t)j0 + (uint64_t)kk, (uint32_t)slot, rld(dl, kk)) ? 1 : 0)) {
+                    js = kk;
+                    move = true;
                 }
             }
-            const double vb = rld(vbl, i);
-            const int pos = idx + di;
-            // every candidate bin at once; dl - vb > 0 <=> dl > vb exactly, and an
-            // accept so decided is final; a reject inside the band is re-decided
-            const double e = (lngc - gl) - vb;
-            const uint64_t acc = __ballot(e > 0.0);
-            const uint64_t band = __ballot(e >= -2.0 * kBand);   // holds acc
-            const uint64_t sel = 1ull << pos;
-            int f = (acc & sel) != 0;
-            if (__builtin_expect(((band & ~acc) & sel) != 0, 0)) {
-                const double delta = rld(lngc - gl, pos);
-                f = __builtin_amdgcn_readfirstlane(
-                    slow_decide(I, T0 + (uint64_t)j0 + (uint64_t)i, (uint32_t)slot, delta) ? 1 : 0);
+            // attempts i..js-1 were rejected or moved within the bin: the bin took
+            // js - i updates; the d = 0 moves among them and a move at js flip
+            const uint64_t below = js >= 64 ? ~0ull : ((1ull << js) - 1);
+            const uint64_t flips = (zero & below) | (move ? (1ull << js) : 0ull);
+            if ((flips >> lane) & 1u) {
+                if (MODEL == 0) atomicXor((unsigned long long*)&lrow[rr], 1ull << cc);
+                else llat[site] = (uint8_t)nv;
             }
-            if (f) {
-                idx = pos;
-                lngc = rld(gl, pos);
-                stale |= rl64(aff, i);
-                if (MODEL == 0) {
-                    const int r0 = (pki >> 4) & 63, c0 = pki >> 10;
-                    const uint64_t m = 1ull << c0;
-                    if (lane == r0) {
-                        rlo ^= (uint32_t)m;
-                        rhi ^= (uint32_t)(m >> 32);
-                    }
-                } else {
-                    if (lane == 0) llat[(pki >> 12) & 4095u] = (uint8_t)nvi;
+            F |= flips;
+            const double rej = (double)(js - i) * incv;
+            lngc += rej;
+            if (lane == idx) gl += rej;
+            if (move) {
+                idx += __builtin_amdgcn_readlane(d, js);
+                lngc = rld(gl, idx) + incv;
+                if (lane == idx) gl += incv;
+                if (__builtin_expect(idx < 4 || idx > 59, 0)) {
+                    store_window();
+                    const int bb = b0 + idx;
+                    b0 = bb - 32 < 0 ? 0 : (bb - 32 > b0max ? b0max : bb - 32);
+                    idx = bb - b0;
+                    load_window();
                 }
-            }
-            lngc += incv;
-            if (lane == idx) gl += incv;
-            if (__builtin_expect(idx < 4 || idx > 59, 0)) {
-                store_window();
-                const int bb = b0 + idx;
-                b0 = bb - 32 < 0 ? 0 : (bb - 32 > b0max ? b0max : bb - 32);
-                idx = bb - b0;
-                load_window();
+                i = js + 1;
+            } else {
+                i = js;                   // js (if < n) is re-evaluated before it is taken
             }
         }
     }
     store_window();
-    row = ((uint64_t)rhi << 32) | rlo;
 
     // ---- write back
     for (int i = lane; i < WB; i += 64) {
@@ -565,7 +558,7 @@ __device__ void sweep_wave(const Inst& I, const Tile& tile, char* smem)
         I.H[(size_t)slot * WB + i] = hv == 0xffffffffu ? 0u : hv;
     }
     if (MODEL == 0) {
-        if (lane < L) I.lat[(size_t)slot * L + lane] = row;
+        if (lane < L) I.lat[(size_t)slot * L + lane] = lrow[lane];
     } else {
         for (int i = lane; i < N; i += 64) I.plat[(size_t)slot * N + i] = llat[i];
     }
@@ -660,7 +653,8 @@ __global__ void __launch_bounds__(256) k_merge(const Inst* __restrict__ insts,
         if (tid < st) red[tid] = red[tid + st] > red[tid] ? red[tid + st] : red[tid];
         __syncthreads();
     }
-    if (tid == 0) okflag = red[0] < __builtin_ldexp(1.0, 52 - sh);
+    // values are multiples of 2^-sh, or of 2^-20 after a warm start: exact below 2^(52 - that)
+    if (tid == 0) okflag = red[0] < __builtin_ldexp(1.0, 52 - (sh > 20 ? sh : 20));
     __syncthreads();
     for (int b = tid; b < WB; b += blockDim.x) base[b] = base[b] - shift;
     for (size_t i = tid; i < (size_t)WB * m; i += blockDim.x) H[i] = 0u;

@@ -127,7 +127,7 @@ def test_gemm_lane_layout_exact(rw):
     # FP32, so the product must match bit for bit: this pins the operand and
     # accumulator lane layout of the matrix instruction
     rng = np.random.default_rng(5)
-    for M_, N_, K in [(32, 32, 16), (64, 96, 48), (128, 64, 256)]:
+    for M_, N_, K in [(64, 64, 32), (128, 192, 96), (128, 64, 256)]:
         A = rng.integers(-8, 9, (M_, K)) / 8.0
         B = rng.integers(-8, 9, (K, N_)) / 8.0
         C = rw.mlp_probe_gemm(A, B)
@@ -136,7 +136,7 @@ def test_gemm_lane_layout_exact(rw):
 
 def test_gemm_rounds_operands_to_bf16(rw):
     rng = np.random.default_rng(6)
-    A = rng.standard_normal((96, 256))
+    A = rng.standard_normal((128, 256))
     B = rng.standard_normal((256, 64))
     C = rw.mlp_probe_gemm(A, B).astype(np.float64)
     Ar, Br = bf16_round(A), bf16_round(B)
@@ -149,7 +149,9 @@ def test_gemm_rounds_operands_to_bf16(rw):
 
 def test_gemm_rejects_ragged_shapes(rw):
     with pytest.raises(rw.MlpError):
-        rw.mlp_probe_gemm(np.ones((30, 16)), np.ones((16, 32)))
+        rw.mlp_probe_gemm(np.ones((30, 32)), np.ones((32, 64)))
+    with pytest.raises(rw.MlpError):
+        rw.mlp_probe_gemm(np.ones((64, 16)), np.ones((16, 64)))
 
 
 # ------------------------------------------------------------ network
