@@ -39,6 +39,7 @@ OPS_PER_ATTEMPT = {"ising": 30, "potts": 37}
 
 LABELS = {
     "ising8": "2D Ising L=8 periodic, 4 windows o=3/4, 1 walker/window, X=1e4, ln f to 2^-20",
+    "ising32": "2D Ising L=32 periodic, 8 windows o=3/4, 16 walkers/window, X=1e4, ln f to 2^-20",
     "ising64": "2D Ising L=64 periodic, 16 windows o=3/4, 64 walkers/window, X=1e4",
     "potts32": "2D 10-state Potts L=32 periodic, 32 windows o=3/4, 128 walkers/window, X=1e4",
     "batch64": "64 independent REWL instances: Ising L 16-64 and Potts q 4/8/10 L 16-32, "
@@ -220,6 +221,12 @@ def main(argv=None):
                     help="only copy a device buffer of this size and exit (a kernel of known "
                          "traffic for scaling the HBM byte counters)")
     ap.add_argument("--wpb", type=int, default=0, help="walkers per block (0 = library choice)")
+    ap.add_argument("--flat-rule", default="mean", choices=["mean", "visits"],
+                    help="--converge: flatness rule (mean: min H >= num/den of the mean; "
+                         "visits: H >= (num/den)/sqrt(ln f) for every level, Eq. (8))")
+    ap.add_argument("--flat", default="", help="--converge: flatness parameter num,den")
+    ap.add_argument("--m", type=int, default=0, help="--converge: walkers per window override")
+    ap.add_argument("--kfinal-override", type=int, default=0, help="--converge: final ln f exponent")
     ap.add_argument("--warm", action="store_true",
                     help="train the DOS network on REWL results of small systems and compare "
                          "time to converge, warm start against plain REWL, on larger targets")
@@ -254,8 +261,16 @@ def main(argv=None):
     label = LABELS[args.workload]
     if args.converge:
         tune = rw.make_tune(args.sweep, args.wpb, 1, 200)
+        kw = dict(kws[0], flat_rule=args.flat_rule)
+        if args.flat:
+            kw["flat"] = tuple(int(v) for v in args.flat.split(","))
+        if args.m:
+            kw["m"] = args.m
+        if args.kfinal_override:
+            kw["kfinal"] = args.kfinal_override
+        label += f"; flatness {kw['flat_rule']} {kw.get('flat', (4, 5))}, m={kw['m']}, kfinal={kw['kfinal']}"
         for sd in [int(x) for x in args.seeds.split(",")]:
-            print(json.dumps(converge(rw, kws[0], label, tune, args.max_seconds, sd)), flush=True)
+            print(json.dumps(converge(rw, kw, label, tune, args.max_seconds, sd)), flush=True)
         return 0
     cfgs = [rw.make_config(**kw) for kw in kws]
     S = sum(kw["n_windows"] * kw["m"] for kw in kws)

@@ -49,14 +49,26 @@ typedef struct {
     int32_t overlap_num;        /* overlap o = num/den with the next lower window, 0<=o<1 */
     int32_t overlap_den;
     int32_t walkers_per_window; /* m: a power of two, 1..1024                            */
-    int32_t flat_num;           /* flat iff min H >= num/den * mean H (Sec. II.A)        */
+    int32_t flat_num;           /* flatness parameter num/den, see flat_rule             */
     int32_t flat_den;
     int32_t lnf_k0;             /* initial ln f = 2^-k0 (Sec. II.A uses ln f = 1: k0=0)  */
     int32_t lnf_kfinal;         /* window converged once k >= kfinal (ln f <= 2^-kfinal) */
     int32_t exchange_enabled;   /* 1: replica exchange (Eq. (1)); 0: independent windows */
     int64_t exchange_interval;  /* flip attempts per walker between exchange steps       */
     uint64_t seed;              /* Philox4x32-10 key                                     */
+    int32_t flat_rule;          /* REWL_FLAT_MEAN or REWL_FLAT_VISITS (below)            */
+    int32_t reserved;           /* must be 0                                             */
 } rewl_config;
+
+/* Flatness rules, tested per walker over the levels of its window that occur;
+ * a window merges once all m walkers have passed (latched):
+ *  REWL_FLAT_MEAN   min H >= (flat_num/flat_den) * mean H, 0 <= num <= den (Sec. II.A,
+ *                   80 %: 4/5);
+ *  REWL_FLAT_VISITS H(E) >= a / sqrt(ln f) for every E, a = flat_num/flat_den
+ *                   (Eq. (8), the Zhou-Bhatt criterion applied to all m walkers);
+ *                   with ln f = 2^-k it is decided exactly as H^2 den^2 >= num^2 2^k;
+ *                   0 <= num, 1 <= den, both <= 2^20.                                */
+enum { REWL_FLAT_MEAN = 0, REWL_FLAT_VISITS = 1 };
 
 /* Sweep variants.  LANE: one walker per lane, draws precomputed for the whole
  * interval by a separate kernel (suits batches of many thousands of walkers).

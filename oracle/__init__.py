@@ -41,13 +41,16 @@ class Config(ctypes.Structure):
                 ("flat_num", ctypes.c_int32), ("flat_den", ctypes.c_int32),
                 ("lnf_k0", ctypes.c_int32), ("lnf_kfinal", ctypes.c_int32),
                 ("exchange_enabled", ctypes.c_int32), ("exchange_interval", ctypes.c_int64),
-                ("seed", ctypes.c_uint64)]
+                ("seed", ctypes.c_uint64), ("flat_rule", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 def make_config(model="ising", q=2, L=8, n_windows=4, overlap=(3, 4), m=1, flat=(4, 5),
-                k0=0, kfinal=20, X=10000, seed=1, exchange=True) -> Config:
+                k0=0, kfinal=20, X=10000, seed=1, exchange=True, flat_rule="mean") -> Config:
+    """flat_rule "mean": min H >= num/den of the mean (Sec. II.A); "visits":
+    H(E) >= (num/den)/sqrt(ln f) for every E, Eq. (8)."""
     return Config(0 if model == "ising" else 1, q, L, n_windows, overlap[0], overlap[1], m,
-                  flat[0], flat[1], k0, kfinal, 1 if exchange else 0, X, seed)
+                  flat[0], flat[1], k0, kfinal, 1 if exchange else 0, X, seed,
+                  {"mean": 0, "visits": 1}[flat_rule], 0)
 
 
 def lib():

@@ -276,7 +276,10 @@ orc_sim* orc_create(const orc_config* c, const uint8_t* mask, const double* init
     if (c->model == 1 && c->q < 3) return NULL;
     if (c->L > 1024) return NULL;
     if (c->walkers_per_window < 1 || ilog2_exact(c->walkers_per_window) < 0) return NULL;
-    if (c->flat_den < 1 || c->flat_num < 0 || c->flat_num > c->flat_den) return NULL;
+    if (c->flat_rule == 0 && (c->flat_den < 1 || c->flat_num < 0 || c->flat_num > c->flat_den)) return NULL;
+    if (c->flat_rule == 1 && (c->flat_den < 1 || c->flat_den > (1 << 20) || c->flat_num < 0 ||
+                              c->flat_num > (1 << 20))) return NULL;
+    if (c->flat_rule != 0 && c->flat_rule != 1) return NULL;
     if (c->lnf_k0 < 0 || c->lnf_kfinal <= c->lnf_k0 || c->lnf_kfinal > 40) return NULL;
     if (c->exchange_interval < 1) return NULL;
     if (mask == NULL && c->model == 1 && c->L < 4) return NULL;
@@ -391,8 +394,11 @@ static void sweep_slot(orc_sim* s, int slot)
     s->E[slot] = E;
 }
 
-/* Flatness (Sec. II.A): no H(E) below flat_num/flat_den of the mean, over  */
-/* the levels of the window that occur; integer form den*min*n >= num*sum. */
+/* Flatness of one walker over the levels of its window that occur.         */
+/* Rule 0 (Sec. II.A): no H(E) below flat_num/flat_den of the mean, in the   */
+/* integer form den*min*n >= num*sum.  Rule 1 (Eq. (8)): every H(E) at least */
+/* a/sqrt(ln f) with a = num/den and ln f = 2^-k, i.e. min^2 den^2 >=        */
+/* num^2 2^k, evaluated in 128-bit integers.                                 */
 static int is_flat(const orc_sim* s, int slot)
 {
     int a = slot / s->m;
@@ -404,6 +410,13 @@ static int is_flat(const orc_sim* s, int slot)
         if (mn < 0 || v < mn) mn = v;
         sum += v;
         ++n;
+    }
+    if (s->c.flat_rule == 1) {
+        const unsigned __int128 lhs = (unsigned __int128)mn * (unsigned __int128)mn * (unsigned __int128)s->c.flat_den *
+                                      (unsigned __int128)s->c.flat_den;
+        const unsigned __int128 rhs = ((unsigned __int128)s->c.flat_num * (unsigned __int128)s->c.flat_num)
+                                      << s->k[a];
+        return lhs >= rhs;
     }
     return (int64_t)s->c.flat_den * mn * n >= (int64_t)s->c.flat_num * sum;
 }

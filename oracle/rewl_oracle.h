@@ -29,13 +29,16 @@ typedef struct {
     int32_t overlap_num;        /* o = overlap_num / overlap_den                      */
     int32_t overlap_den;
     int32_t walkers_per_window; /* m, a power of two                                  */
-    int32_t flat_num;           /* flatness: min H >= flat_num/flat_den * mean H      */
+    int32_t flat_num;           /* flatness parameter, see flat_rule                  */
     int32_t flat_den;
     int32_t lnf_k0;             /* initial ln f = 2^-k0                               */
     int32_t lnf_kfinal;         /* window converged once k >= kfinal                  */
     int32_t exchange_enabled;   /* 1 = replica exchange on                            */
     int64_t exchange_interval;  /* flip attempts per walker between exchanges         */
     uint64_t seed;              /* Philox key                                         */
+    int32_t flat_rule;          /* 0: min H >= num/den mean H (Sec. II.A);
+                                   1: H(E) >= (num/den)/sqrt(ln f) for all E, Eq. (8)   */
+    int32_t reserved;
 } orc_config;
 
 typedef struct orc_sim orc_sim;

@@ -40,7 +40,7 @@ class rewl_config(ctypes.Structure):
                 ("flat_num", ctypes.c_int32), ("flat_den", ctypes.c_int32),
                 ("lnf_k0", ctypes.c_int32), ("lnf_kfinal", ctypes.c_int32),
                 ("exchange_enabled", ctypes.c_int32), ("exchange_interval", ctypes.c_int64),
-                ("seed", ctypes.c_uint64)]
+                ("seed", ctypes.c_uint64), ("flat_rule", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 REWL_SWEEP_AUTO, REWL_SWEEP_LANE, REWL_SWEEP_WAVE = 0, 1, 2
@@ -130,13 +130,18 @@ def _p(a: np.ndarray):
     return a.ctypes.data_as(_vp)
 
 
+REWL_FLAT_MEAN, REWL_FLAT_VISITS = 0, 1
+
+
 def make_config(model="ising", q=2, L=8, n_windows=4, overlap=(3, 4), m=1, flat=(4, 5), k0=0,
-                kfinal=20, X=10000, seed=1, exchange=True) -> rewl_config:
+                kfinal=20, X=10000, seed=1, exchange=True, flat_rule="mean") -> rewl_config:
     """Problem statement of Sec. II.A / IV: model, L, h windows with overlap o,
-    m walkers per window, flatness num/den, ln f = 2^-k0 .. 2^-kfinal, X attempts
-    per walker between exchanges, Philox seed."""
+    m walkers per window, flatness num/den (rule "mean": min H >= num/den of the
+    mean; rule "visits": H >= (num/den)/sqrt(ln f), Eq. (8)), ln f = 2^-k0 ..
+    2^-kfinal, X attempts per walker between exchanges, Philox seed."""
     return rewl_config(0 if model == "ising" else 1, q, L, n_windows, overlap[0], overlap[1], m,
-                       flat[0], flat[1], k0, kfinal, 1 if exchange else 0, X, seed)
+                       flat[0], flat[1], k0, kfinal, 1 if exchange else 0, X, seed,
+                       {"mean": REWL_FLAT_MEAN, "visits": REWL_FLAT_VISITS}[flat_rule], 0)
 
 
 # ------------------------------------------------------------ C-ABI mirrors

@@ -95,8 +95,14 @@ rewl_status validate(const rewl_config& c)
         return fail(REWL_E_INVALID, "overlap must be num/den in [0, 1)");
     if (c.walkers_per_window < 1 || c.walkers_per_window > 1024 || ilog2_exact(c.walkers_per_window) < 0)
         return fail(REWL_E_INVALID, "walkers_per_window must be a power of two in [1, 1024]");
-    if (c.flat_den < 1 || c.flat_num < 0 || c.flat_num > c.flat_den)
+    if (c.flat_rule != REWL_FLAT_MEAN && c.flat_rule != REWL_FLAT_VISITS)
+        return fail(REWL_E_INVALID, "flat_rule must be REWL_FLAT_MEAN or REWL_FLAT_VISITS");
+    if (c.reserved != 0) return fail(REWL_E_INVALID, "reserved must be 0");
+    if (c.flat_rule == REWL_FLAT_MEAN && (c.flat_den < 1 || c.flat_num < 0 || c.flat_num > c.flat_den))
         return fail(REWL_E_INVALID, "flatness must be num/den in [0, 1]");
+    if (c.flat_rule == REWL_FLAT_VISITS &&
+        (c.flat_den < 1 || c.flat_num < 0 || c.flat_den > (1 << 20) || c.flat_num > (1 << 20)))
+        return fail(REWL_E_INVALID, "Eq. (8) needs a = num/den with 0 <= num, 1 <= den, both <= 2^20");
     if (c.lnf_k0 < 0 || c.lnf_kfinal <= c.lnf_k0 || c.lnf_kfinal > 40)
         return fail(REWL_E_INVALID, "need 0 <= lnf_k0 < lnf_kfinal <= 40");
     if (c.exchange_interval < 1 || c.exchange_interval > (int64_t(1) << 31))
@@ -421,7 +427,7 @@ static rewl_status create_impl(const rewl_config* cfgs, int32_t n, void* hip_str
         std::memset(&d, 0, sizeof(d));
         d.model = c.model; d.q = c.model ? c.q : 2; d.L = c.L; d.N = hi.N; d.W = hi.W; d.h = hi.h;
         d.m = hi.m; d.S = hi.S; d.WB = hi.WB; d.log2m = hi.log2m; d.flat_num = c.flat_num;
-        d.flat_den = c.flat_den; d.kfinal = c.lnf_kfinal; d.exch = c.exchange_enabled; d.wpr = hi.wpr;
+        d.flat_den = c.flat_den; d.flat_rule = c.flat_rule; d.kfinal = c.lnf_kfinal; d.exch = c.exchange_enabled; d.wpr = hi.wpr;
         d.X = c.exchange_interval; d.k0 = (uint32_t)c.seed; d.k1 = (uint32_t)(c.seed >> 32);
         d.XP = (c.exchange_interval + 31) / 32 * 32;   // two draw chunks of 16
         if ((uint64_t)d.XP * hi.S >= (uint64_t(1) << 32))

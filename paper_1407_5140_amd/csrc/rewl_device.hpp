@@ -180,7 +180,7 @@ struct InstCtr {
 struct Inst {
     // problem
     int32_t model, q, L, N, W, h, m, S, WB, log2m;
-    int32_t flat_num, flat_den, kfinal, exch, wpr;
+    int32_t flat_num, flat_den, kfinal, exch, wpr, flat_rule;
     int64_t X;
     int64_t XP;         // row stride of the draw buffers: X rounded up to 32
     uint32_t k0, k1;
@@ -206,6 +206,21 @@ struct Inst {
     int32_t* merges;    // [h] interval of each window's last merge
     InstCtr* ctr;
 };
+
+// Flatness of one walker from the minimum and sum of its counts over the n
+// levels of its window that occur.  Rule 0 (Sec. II.A): min >= num/den of the
+// mean.  Rule 1 (Eq. (8)): min >= (num/den) / sqrt(ln f), ln f = 2^-k, decided
+// exactly as min^2 den^2 >= num^2 2^k (both below 2^105).
+__device__ __forceinline__ bool walker_flat(const Inst& I, uint32_t mn, uint64_t sum, int64_t n, int k)
+{
+    if (I.flat_rule == 1) {
+        const unsigned __int128 lhs = (unsigned __int128)((uint64_t)mn * mn) *
+                                      (uint64_t)((int64_t)I.flat_den * I.flat_den);
+        const unsigned __int128 rhs = (unsigned __int128)((uint64_t)((int64_t)I.flat_num * I.flat_num)) << k;
+        return lhs >= rhs;
+    }
+    return (int64_t)I.flat_den * (int64_t)mn * n >= (int64_t)I.flat_num * (int64_t)sum;
+}
 
 // A sweep tile: nw consecutive walkers of one window of one instance.
 struct Tile {

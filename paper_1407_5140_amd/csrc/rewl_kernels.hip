@@ -284,8 +284,8 @@ __device__ void sweep_tile(const Inst& I, const Tile& tile, char* smem)
             for (int w = lane; w < N; w += nthr) I.plat[(size_t)(slot0 + l) * N + w] = lat[(w << lnw) + l];
     }
 
-    // ---- flatness of each walker (Sec. II.A): min H >= num/den * mean H over
-    //      the levels of the window that occur; latched until the window merges
+    // ---- flatness of each walker (Sec. II.A, or Eq. (8)) over the levels of the
+    //      window that occur; latched until the window merges
     if (inc && lane < nw) {
         uint32_t mn = 0xffffffffu;
         uint64_t sum = 0;
@@ -295,9 +295,7 @@ __device__ void sweep_tile(const Inst& I, const Tile& tile, char* smem)
             sum += v == 0xffffffffu ? 0u : v;
         }
         const int slot = slot0 + lane;
-        const int64_t n = I.nreach[a];
-        if ((int64_t)I.flat_den * (int64_t)mn * n >= (int64_t)I.flat_num * (int64_t)sum)
-            I.flat[slot] = 1;
+        if (walker_flat(I, mn, sum, I.nreach[a], k)) I.flat[slot] = 1;
         if (sum + (uint64_t)X >= 0xffffffffull) atomicOr(&I.ctr->err, kErrOverflow);
     }
 }
@@ -588,9 +586,7 @@ __device__ void sweep_wave(const Inst& I, const Tile& tile, char* smem)
         }
         if (lane == 0) {
             const uint64_t tot = ((uint64_t)shi << 32) | slo;
-            const int64_t nreach = I.nreach[a];
-            if ((int64_t)I.flat_den * (int64_t)mn * nreach >= (int64_t)I.flat_num * (int64_t)tot)
-                I.flat[slot] = 1;
+            if (walker_flat(I, mn, tot, I.nreach[a], k)) I.flat[slot] = 1;
             if (tot + (uint64_t)X >= 0xffffffffull) atomicOr(&I.ctr->err, kErrOverflow);
         }
     }

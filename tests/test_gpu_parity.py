@@ -103,6 +103,9 @@ SMALL = [
     dict(model="potts", q=255, L=6, n_windows=2, m=8, kfinal=6, X=1000, seed=19),  # largest q
     dict(model="ising", L=4, n_windows=1, m=4, kfinal=10, X=1, seed=23),         # one window, X = 1
     dict(model="ising", L=12, n_windows=5, m=4, kfinal=10, X=700, seed=29, exchange=False),
+    # Eq. (8): every level visited at least a / sqrt(ln f) times by every walker
+    dict(model="ising", L=16, n_windows=4, m=8, kfinal=12, X=3000, seed=31, flat_rule="visits", flat=(1, 1)),
+    dict(model="potts", q=10, L=8, n_windows=4, m=4, kfinal=12, X=3000, seed=37, flat_rule="visits", flat=(3, 2)),
 ]
 
 
@@ -111,7 +114,8 @@ def _tune(rw, kind, wpb=0, graph=0, poll=8):
 
 
 @pytest.mark.parametrize("kind", ["lane", "wave"])
-@pytest.mark.parametrize("kw", SMALL, ids=lambda kw: f"{kw['model']}-L{kw['L']}-h{kw['n_windows']}-m{kw['m']}")
+@pytest.mark.parametrize("kw", SMALL, ids=lambda kw: f"{kw['model']}-L{kw['L']}-h{kw['n_windows']}-m{kw['m']}"
+                                                   f"{'-' + kw['flat_rule'] if 'flat_rule' in kw else ''}")
 def test_lockstep_small(rw, kw, kind):
     steps = 40 if kw["X"] > 1 else 3000
     gpu, _, _ = _lockstep(rw, kw, steps, tune=_tune(rw, kind), every=1 if kw["X"] > 1 else 500)

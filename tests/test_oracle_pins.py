@@ -372,3 +372,55 @@ def test_rewl_brute_force_potts_q3_L3(golden):
     out, _ = O.concat(c, mask, sim.pieces())
     ok = mask > 0
     assert np.abs(out[ok] - exact[ok]).max() < 0.12
+
+
+# ------------------------------------------------------------ Eq. (8) flatness
+def _visits_flat(H, mask_w, k, num, den):
+    """Eq. (8) on one walker's counts, in Python integers: min H >= (num/den) 2^(k/2)."""
+    mn = int(min(int(v) for v, ok in zip(H, mask_w) if ok))
+    return (mn * den) ** 2 >= num * num * 2 ** k
+
+
+@pytest.mark.parametrize("num,den,model,q,L", [(1, 1, "ising", 2, 8), (3, 2, "potts", 4, 5), (5, 1, "ising", 2, 6)])
+def test_visits_rule_latches_exactly_eq8(num, den, model, q, L):
+    """Between merges a walker's counts only grow, so its latched flag must equal
+    Eq. (8) evaluated on its current counts; checked interval by interval."""
+    cfg = O.make_config(model, q=q, L=L, n_windows=2, m=2, kfinal=14, X=400, seed=3,
+                        flat_rule="visits", flat=(num, den))
+    sim = O.Sim(cfg)
+    mask = O.mask_rule(cfg)
+    lo, hi = O.layout(cfg)
+    prev_k = sim.state()["k"].copy()
+    checked = merged = 0
+    for _ in range(400):
+        done = sim.run(1)
+        st = sim.state()
+        for a in range(cfg.n_windows):
+            if st["done"][a]:
+                continue
+            if st["k"][a] != prev_k[a]:
+                merged += 1
+                assert st["k"][a] == prev_k[a] + 1
+                assert not st["flat"][a * 2:(a + 1) * 2].any() and not st["H"][a * 2:(a + 1) * 2].any()
+                continue
+            mw = mask[lo[a]:hi[a] + 1]
+            for r in range(2):
+                slot = a * 2 + r
+                want = _visits_flat(st["H"][slot][: hi[a] - lo[a] + 1], mw, int(st["k"][a]), num, den)
+                assert bool(st["flat"][slot]) == want
+                checked += 1
+        prev_k = st["k"].copy()
+        if done:
+            break
+    assert merged >= 4 and checked > 50
+
+
+def test_visits_rule_with_a_zero_merges_every_interval():
+    # a = 0: every count satisfies H >= 0, so each window merges at every interval
+    cfg = O.make_config("ising", L=8, n_windows=3, m=4, k0=2, kfinal=9, X=50, seed=9,
+                        flat_rule="visits", flat=(0, 1))
+    sim = O.Sim(cfg)
+    for t in range(1, 8):
+        done = sim.run(1)
+        assert list(sim.state()["k"]) == [2 + t] * 3
+        assert done == (t == 7)
