@@ -48,7 +48,7 @@ LABELS = {
 
 
 # rocprofv3 summaries holding the HBM byte counters of a workload's sweep kernel
-PROFILES = {"ising64": "k_sweep_wave_ising_L64.txt", "potts32": "k_sweep_potts_q10_L32.txt"}
+PROFILES = {"ising64": "k_sweep_wave_ising_L64.txt", "potts32": "k_sweep_wave_potts_q10_L32.txt"}
 KERNEL_SOURCES = ("paper_1407_5140_amd/csrc/rewl_kernels.hip", "paper_1407_5140_amd/csrc/rewl_device.hpp")
 
 
@@ -203,6 +203,58 @@ def warm_start_study(rw, args) -> dict:
             "network": info, "targets": out}
 
 
+def exchange_study(rw, args) -> dict:
+    """Replica exchange on against off, and the exchange interval, on the paper's
+    kind of test (Sec. IV: a Potts model split into 15 windows): attempts per
+    walker until every window reaches ln f = 2^-kfinal, over several seeds.  All
+    settings run as independent instances of one batch; the count of attempts is
+    exact and machine-independent."""
+    from paper_1407_5140_amd import warm as Wm
+    base = dict(model="potts", q=10, L=args.study_L, n_windows=15, m=1, kfinal=args.study_kfinal)
+    settings = [("exchange", 1000), ("exchange", 10000), ("exchange", 100000), ("none", 10000)]
+    kws, tags = [], []
+    for mode, X in settings:
+        for sd in range(1, args.study_seeds + 1):
+            kws.append(dict(base, X=X, seed=100 + sd, exchange=(mode == "exchange")))
+            tags.append((mode, X))
+    log = lambda m: print(f"[exchange] {m}", file=sys.stderr, flush=True)
+    g, res = Wm.run_to_convergence(kws, args.max_seconds, log=log)
+    g.close()
+    rows = []
+    for mode, X in settings:
+        att = [r["intervals"] * X for r, t in zip(res, tags) if t == (mode, X) and r["converged"]]
+        n_conv = sum(1 for r, t in zip(res, tags) if t == (mode, X) and r["converged"])
+        rows.append({"exchange": mode == "exchange", "X": X, "converged": n_conv,
+                     "attempts_per_walker": att,
+                     "median": float(np.median(att)) if att else None})
+    ref = next(r for r in rows if not r["exchange"])["median"]
+    for r in rows:
+        r["speedup_vs_no_exchange"] = (ref / r["median"]) if (ref and r["median"]) else None
+    return {"mode": "replica exchange on/off", "workload": f"Potts q=10 L={args.study_L}, 15 windows o=3/4, "
+            f"1 walker/window, ln f 1 -> 2^-{args.study_kfinal}", "settings": rows}
+
+
+def mlp_bench(rw, args) -> dict:
+    """Training throughput of the DOS network (3 x 256 GELU, batch 4096) on rows
+    shaped like the warm-start data; matrix-core work per step: six 4096 x 256 x 256
+    products (two forward, two weight gradients, two input gradients)."""
+    rng = np.random.default_rng(1)
+    n = 16384
+    L = rng.choice([16.0, 24.0, 32.0, 48.0], n)
+    x = np.stack([rng.uniform(-2, 2, n), 1.0 / L, rng.choice([2.0, 4.0, 8.0, 10.0], n)], axis=1)
+    t = np.log(2.0) * (1 - (x[:, 0] / 2) ** 2) + 0.01 * x[:, 1]
+    net = rw.Mlp(3, 256, 3, max_batch=4096, seed=1)
+    net.fit(x, t, args.mlp_warmup_steps, batch=4096, lr=1e-3)
+    t0 = time.perf_counter()
+    loss = net.fit(x, t, args.mlp_steps, batch=4096, lr=1e-3)
+    dt = time.perf_counter() - t0
+    net.close()
+    flops = 6 * 2 * 4096 * 256 * 256
+    return {"mode": "DOS network training", "batch": 4096, "steps": args.mlp_steps,
+            "ms_per_step": dt * 1e3 / args.mlp_steps, "matrix_tflops_per_s": flops * args.mlp_steps / dt / 1e12,
+            "gemm_flops_per_step": flops, "last_loss": loss}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -227,6 +279,13 @@ def main(argv=None):
     ap.add_argument("--flat", default="", help="--converge: flatness parameter num,den")
     ap.add_argument("--m", type=int, default=0, help="--converge: walkers per window override")
     ap.add_argument("--kfinal-override", type=int, default=0, help="--converge: final ln f exponent")
+    ap.add_argument("--mlp-bench", action="store_true", help="time the DOS network's training steps")
+    ap.add_argument("--mlp-warmup-steps", type=int, default=20)
+    ap.add_argument("--exchange-study", action="store_true",
+                    help="attempts to converge with replica exchange on/off and several intervals")
+    ap.add_argument("--study-L", type=int, default=24)
+    ap.add_argument("--study-kfinal", type=int, default=14)
+    ap.add_argument("--study-seeds", type=int, default=4)
     ap.add_argument("--warm", action="store_true",
                     help="train the DOS network on REWL results of small systems and compare "
                          "time to converge, warm start against plain REWL, on larger targets")
@@ -256,6 +315,12 @@ def main(argv=None):
 
     if args.warm:
         print(json.dumps(warm_start_study(rw, args)), flush=True)
+        return 0
+    if args.mlp_bench:
+        print(json.dumps(mlp_bench(rw, args)), flush=True)
+        return 0
+    if args.exchange_study:
+        print(json.dumps(exchange_study(rw, args)), flush=True)
         return 0
     kws = workload(args.workload)
     label = LABELS[args.workload]
