@@ -162,6 +162,8 @@ def warm_start_study(rw, args) -> dict:
     from paper_1407_5140_amd import warm as Wm
     types = [("ising", 2, 16), ("ising", 2, 24), ("ising", 2, 32), ("potts", 4, 16), ("potts", 4, 24),
              ("potts", 8, 16), ("potts", 8, 24), ("potts", 10, 16), ("potts", 10, 24)]
+    if args.train_types == "batch":
+        types = Wm.TRAIN_TYPES            # every type of the 64-instance batch with L <= 48
     log = lambda m: print(f"[warm] {m}", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     kws = Wm.training_workload(types, m=32, kfinal=args.train_kfinal)
@@ -174,15 +176,18 @@ def warm_start_study(rw, args) -> dict:
         f"{len(t)} rows, {t_train:.1f} s")
     net, info = Wm.train(x, t, steps=args.mlp_steps, batch=4096, lr=1e-3)
     log(f"network: {info}")
-    targets = [dict(model="potts", q=10, L=32, n_windows=16, m=32, kfinal=args.kfinal, X=10000, seed=1),
-               dict(model="ising", q=2, L=48, n_windows=32, m=32, kfinal=args.kfinal, X=10000, seed=1)]
+    known = {"potts32": dict(model="potts", q=10, L=32, n_windows=16, m=32),
+             "ising48": dict(model="ising", q=2, L=48, n_windows=32, m=32),
+             "ising64": dict(model="ising", q=2, L=64, n_windows=16, m=64)}
+    targets = [dict(known[t], kfinal=args.kfinal, X=10000, seed=1) for t in args.warm_targets.split(",")]
+    modes = args.warm_modes.split(",")
     out = []
     for kw in targets:
         label = f"{kw['model']} q={kw['q']} L={kw['L']} h={kw['n_windows']} m={kw['m']}"
         tab = Wm.warm_table(net, kw)
         row = {"workload": label, "kfinal": kw["kfinal"], "k0_warm": args.k0}
         ex = exact_ln_g(kw)
-        for mode in ("warm", "plain"):
+        for mode in modes:
             k = dict(kw, k0=args.k0 if mode == "warm" else 0)
             gg, rr = Wm.run_to_convergence([k], args.target_seconds,
                                            warm_tables=[tab] if mode == "warm" else None, log=log)
@@ -190,11 +195,13 @@ def warm_start_study(rw, args) -> dict:
             if ex is not None and r["converged"]:
                 lng, _ = gg.concat(0)
                 okb = np.isfinite(ex)
-                r["eps_max"] = float(np.max(np.abs(lng[okb] - ex[okb]) / np.abs(ex[okb])))
+                eps = np.abs(lng[okb] - ex[okb]) / np.abs(ex[okb])
+                r["eps_max"] = float(eps.max())
+                r["eps_mean"] = float(eps.mean())
             gg.close()
             row[mode] = r
             log(f"{label} {mode}: {r}")
-        if row["warm"]["converged"] and row["plain"]["converged"]:
+        if "warm" in row and "plain" in row and row["warm"]["converged"] and row["plain"]["converged"]:
             row["speedup"] = row["plain"]["seconds"] / row["warm"]["seconds"]
         out.append(row)
     net.close()
@@ -290,6 +297,10 @@ def main(argv=None):
                     help="train the DOS network on REWL results of small systems and compare "
                          "time to converge, warm start against plain REWL, on larger targets")
     ap.add_argument("--train-kfinal", type=int, default=16)
+    ap.add_argument("--train-types", default="small", choices=["small", "batch"],
+                    help="--warm: training instances (small: L <= 32/24; batch: the batch's types, L <= 48)")
+    ap.add_argument("--warm-targets", default="potts32,ising48")
+    ap.add_argument("--warm-modes", default="warm,plain")
     ap.add_argument("--kfinal", type=int, default=18, help="--warm: targets' final ln f = 2^-kfinal")
     ap.add_argument("--k0", type=int, default=10, help="--warm: warm start's initial ln f = 2^-k0")
     ap.add_argument("--mlp-steps", type=int, default=4000)
