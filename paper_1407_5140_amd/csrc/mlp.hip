@@ -182,13 +182,20 @@ __global__ void k_colsum_part(const T* __restrict__ Mx, int ldm, int Bn, int H,
         if (k < K) part[((size_t)z * K + k) * H + j] = acc[k];
 }
 
-__global__ void k_colsum_final(const float* __restrict__ part, int Z, int KH, float* __restrict__ out)
+// out[e] = sum over chunks z of part[z*KH + e]: 4 threads per output, each over
+// every fourth chunk, then the 4 sums added in a fixed order (deterministic)
+__global__ void __launch_bounds__(256) k_colsum_final(const float* __restrict__ part, int Z, int KH,
+                                                      float* __restrict__ out)
 {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= KH) return;
+    __shared__ float red[4][64];
+    const int t = threadIdx.x, c = t & 63, g = t >> 6;
+    const int e = blockIdx.x * 64 + c;
     float s = 0.f;
-    for (int z = 0; z < Z; ++z) s += part[(size_t)z * KH + e];
-    out[e] = s;
+    if (e < KH)
+        for (int z = g; z < Z; z += 4) s += part[(size_t)z * KH + e];
+    red[g][c] = s;
+    __syncthreads();
+    if (g == 0 && e < KH) out[e] = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
 }
 
 // first layer: pre = x W1 + b1 (K = in_dim), act = gelu(pre) in BF16
@@ -351,7 +358,7 @@ void colsum(mlp_handle* h, const T* Mx, int ldm, int B, int H, const float* W, i
     const int Z = (B + h->crow - 1) / h->crow, K = nw + ones;
     hipLaunchKernelGGL(k_colsum_part<T>, dim3((H + 63) / 64, Z), dim3(64), 0, h->stream, Mx, ldm, B, H, W, ldw,
                        nw, ones, h->crow, h->cpart);
-    hipLaunchKernelGGL(k_colsum_final, grid1(K * H), dim3(256), 0, h->stream, h->cpart, Z, K * H, out);
+    hipLaunchKernelGGL(k_colsum_final, dim3((K * H + 63) / 64), dim3(256), 0, h->stream, h->cpart, Z, K * H, out);
 }
 
 // forward pass of B rows (B a multiple of 64) already in xb; y written
@@ -480,7 +487,7 @@ rewl_status mlp_create(const mlp_config* c, void* hip_stream, mlp_handle** out)
     // split-K partials: at most 16 splits and 64 MiB
     while (h->Smax < 16 && (size_t)2 * h->Smax * H * H * 4 <= ((size_t)64 << 20)) h->Smax *= 2;
     if (s == REWL_OK && h->Smax > 1) s = h->alloc(&h->kpart, (size_t)h->Smax * H * H);
-    h->crow = std::max(64, h->Bmax / 256);
+    h->crow = std::max(16, h->Bmax / 1024);
     if (s == REWL_OK) s = h->alloc(&h->cpart, (size_t)((h->Bmax + h->crow - 1) / h->crow) * kColK * H);
     if (s != REWL_OK) return bail(s);
     // initial weights: uniform(-1/sqrt(fan_in), 1/sqrt(fan_in)) from a fixed hash, biases 0

@@ -484,56 +484,58 @@ __device__ void sweep_wave(const Inst& I, const Tile& tile, char* smem)
         if (lane < n) lmap[site] = 0;
         const uint64_t live = n == 64 ? ~0ull : ((1ull << n) - 1);
         uint64_t F = 0;                   // attempts flipped since the lanes last evaluated
+        // B = lngc - i incv: with it, lane j's ln g difference is B - gp + j incv
+        double B = lngc;
 
         int i = 0;
         while (i < n) {
             const uint64_t run = live & (~0ull << i);
-            if (F != 0 && (__builtin_amdgcn_ballot_w64((pm & F) != 0) & run) != 0) {
-                evaluate();
-                F = 0;
-            }
             const int pos = idx + d;
             const double gp = __builtin_bit_cast(
                 double, ((uint64_t)shfl32((uint32_t)(__builtin_bit_cast(uint64_t, gl) >> 32), pos) << 32) |
                             shfl32((uint32_t)__builtin_bit_cast(uint64_t, gl), pos));
             // ln g now - ln g of the candidate bin, exact
-            const double dl = (lngc - gp) + (laneinc - (double)i * incv);
+            const double dl = (B - gp) + laneinc;
             const uint64_t zall = __builtin_amdgcn_ballot_w64(d == 0);
             const uint64_t gt = __builtin_amdgcn_ballot_w64(dl > vbl);
             const uint64_t ge = __builtin_amdgcn_ballot_w64(dl >= vbl2);     // holds gt
             const uint64_t zero = zall & run;
             const uint64_t acc = gt & ~zall & run;
             uint64_t amb = ge & ~gt & ~zall & run;
-            const uint64_t hit = __builtin_amdgcn_ballot_w64((pm & zero) != 0) & run;
-            // an attempt both accepted and out of date is out of date: re-evaluated first
+            // out of date: an earlier flip (since the lanes evaluated, or a d = 0 move
+            // of this run) lies in the attempt's neighbourhood.  Accepted and out of
+            // date counts as out of date: it is re-evaluated before it is taken.
+            const uint64_t hit = __builtin_amdgcn_ballot_w64((pm & (zero | F)) != 0) & run;
             const uint64_t stop = acc | hit;
             int js = stop ? (int)__builtin_ctzll(stop) : n;
+            uint64_t below = (stop & (~stop + 1)) - 1;                     // lanes below js
             bool move = ((acc & ~hit) >> js) & 1u;
             // an attempt inside the guard band is decided exactly, in order
-            while (__builtin_expect((amb & (js >= 64 ? ~0ull : ((1ull << js) - 1))) != 0, 0)) {
+            while (__builtin_expect((amb & below) != 0, 0)) {
                 const int kk = (int)__builtin_ctzll(amb);
                 amb &= amb - 1;
                 if (__builtin_amdgcn_readfirstlane(
                         slow_decide(I, T0 + (uint64_t)j0 + (uint64_t)kk, (uint32_t)slot, rld(dl, kk)) ? 1 : 0)) {
                     js = kk;
+                    below = (1ull << kk) - 1;
                     move = true;
                 }
             }
             // attempts i..js-1 were rejected or moved within the bin: the bin took
             // js - i updates; the d = 0 moves among them and a move at js flip
-            const uint64_t below = js >= 64 ? ~0ull : ((1ull << js) - 1);
             const uint64_t flips = (zero & below) | (move ? (1ull << js) : 0ull);
-            if ((flips >> lane) & 1u) {
-                if (MODEL == 0) atomicXor((unsigned long long*)&lrow[rr], 1ull << cc);
-                else llat[site] = (uint8_t)nv;
+            if (flips) {
+                if ((flips >> lane) & 1u) {
+                    if (MODEL == 0) atomicXor((unsigned long long*)&lrow[rr], 1ull << cc);
+                    else llat[site] = (uint8_t)nv;
+                }
+                F |= flips;
             }
-            F |= flips;
-            const double rej = (double)(js - i) * incv;
-            lngc += rej;
-            if (lane == idx) gl += rej;
+            const double jsinc = (double)js * incv;
+            if (lane == idx) gl = B + jsinc;
             if (move) {
                 idx += __builtin_amdgcn_readlane(d, js);
-                lngc = rld(gl, idx) + incv;
+                B = rld(gl, idx) - jsinc;
                 if (lane == idx) gl += incv;
                 if (__builtin_expect(idx < 4 || idx > 59, 0)) {
                     store_window();
@@ -544,9 +546,14 @@ __device__ void sweep_wave(const Inst& I, const Tile& tile, char* smem)
                 }
                 i = js + 1;
             } else {
-                i = js;                   // js (if < n) is re-evaluated before it is taken
+                i = js;
+                if (js < n) {             // attempt js is out of date: evaluate again
+                    evaluate();
+                    F = 0;
+                }
             }
         }
+        lngc = B + (double)n * incv;
     }
     store_window();
 
