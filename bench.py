@@ -164,9 +164,12 @@ def warm_start_study(rw, args) -> dict:
              ("potts", 8, 16), ("potts", 8, 24), ("potts", 10, 16), ("potts", 10, 24)]
     if args.train_types == "batch":
         types = Wm.TRAIN_TYPES            # every type of the 64-instance batch with L <= 48
+    elif args.train_types == "tiny":
+        types = [(mo, q, L) for (mo, q) in (("ising", 2), ("potts", 4), ("potts", 8), ("potts", 10))
+                 for L in (8, 12)]
     log = lambda m: print(f"[warm] {m}", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    kws = Wm.training_workload(types, m=32, kfinal=args.train_kfinal)
+    kws = Wm.training_workload(types, m=32 if args.train_types != "tiny" else 16, kfinal=args.train_kfinal)
     g, res = Wm.run_to_convergence(kws, args.max_seconds, log=log)
     ok = [r["converged"] for r in res]
     x, t = Wm.training_rows(g, kws, ok)
@@ -176,14 +179,17 @@ def warm_start_study(rw, args) -> dict:
         f"{len(t)} rows, {t_train:.1f} s")
     net, info = Wm.train(x, t, steps=args.mlp_steps, batch=4096, lr=1e-3)
     log(f"network: {info}")
-    known = {"potts32": dict(model="potts", q=10, L=32, n_windows=16, m=32),
+    known = {"potts16": dict(model="potts", q=10, L=16, n_windows=8, m=16),
+             "ising24": dict(model="ising", q=2, L=24, n_windows=8, m=16),
+             "potts32": dict(model="potts", q=10, L=32, n_windows=16, m=32),
              "ising48": dict(model="ising", q=2, L=48, n_windows=32, m=32),
              "ising64": dict(model="ising", q=2, L=64, n_windows=16, m=64)}
-    targets = [dict(known[t], kfinal=args.kfinal, X=10000, seed=1) for t in args.warm_targets.split(",")]
+    targets = [dict(known[t], kfinal=args.kfinal, X=10000, seed=sd) for t in args.warm_targets.split(",")
+               for sd in range(1, args.warm_seeds + 1)]
     modes = args.warm_modes.split(",")
     out = []
     for kw in targets:
-        label = f"{kw['model']} q={kw['q']} L={kw['L']} h={kw['n_windows']} m={kw['m']}"
+        label = f"{kw['model']} q={kw['q']} L={kw['L']} h={kw['n_windows']} m={kw['m']} seed={kw['seed']}"
         tab = Wm.warm_table(net, kw)
         row = {"workload": label, "kfinal": kw["kfinal"], "k0_warm": args.k0}
         ex = exact_ln_g(kw)
@@ -297,8 +303,10 @@ def main(argv=None):
                     help="train the DOS network on REWL results of small systems and compare "
                          "time to converge, warm start against plain REWL, on larger targets")
     ap.add_argument("--train-kfinal", type=int, default=16)
-    ap.add_argument("--train-types", default="small", choices=["small", "batch"],
-                    help="--warm: training instances (small: L <= 32/24; batch: the batch's types, L <= 48)")
+    ap.add_argument("--train-types", default="small", choices=["tiny", "small", "batch"],
+                    help="--warm: training instances (tiny: L 8 and 12; small: L <= 32/24; batch: the "
+                         "batch's types, L <= 48)")
+    ap.add_argument("--warm-seeds", type=int, default=1)
     ap.add_argument("--warm-targets", default="potts32,ising48")
     ap.add_argument("--warm-modes", default="warm,plain")
     ap.add_argument("--kfinal", type=int, default=18, help="--warm: targets' final ln f = 2^-kfinal")

@@ -182,20 +182,24 @@ __global__ void k_colsum_part(const T* __restrict__ Mx, int ldm, int Bn, int H,
         if (k < K) part[((size_t)z * K + k) * H + j] = acc[k];
 }
 
-// out[e] = sum over chunks z of part[z*KH + e]: 4 threads per output, each over
-// every fourth chunk, then the 4 sums added in a fixed order (deterministic)
+// out[e] = sum over chunks z of part[z*KH + e]: 16 threads per output, each over
+// every 16th chunk, then the 16 sums added pairwise in a fixed order (deterministic)
 __global__ void __launch_bounds__(256) k_colsum_final(const float* __restrict__ part, int Z, int KH,
                                                       float* __restrict__ out)
 {
-    __shared__ float red[4][64];
-    const int t = threadIdx.x, c = t & 63, g = t >> 6;
-    const int e = blockIdx.x * 64 + c;
+    __shared__ float red[16][17];
+    const int t = threadIdx.x, c = t & 15, g = t >> 4;
+    const int e = blockIdx.x * 16 + c;
     float s = 0.f;
     if (e < KH)
-        for (int z = g; z < Z; z += 4) s += part[(size_t)z * KH + e];
+        for (int z = g; z < Z; z += 16) s += part[(size_t)z * KH + e];
     red[g][c] = s;
     __syncthreads();
-    if (g == 0 && e < KH) out[e] = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
+    for (int w = 8; w > 0; w >>= 1) {
+        if (g < w) red[g][c] += red[g + w][c];
+        __syncthreads();
+    }
+    if (g == 0 && e < KH) out[e] = red[0][c];
 }
 
 // first layer: pre = x W1 + b1 (K = in_dim), act = gelu(pre) in BF16
@@ -358,7 +362,7 @@ void colsum(mlp_handle* h, const T* Mx, int ldm, int B, int H, const float* W, i
     const int Z = (B + h->crow - 1) / h->crow, K = nw + ones;
     hipLaunchKernelGGL(k_colsum_part<T>, dim3((H + 63) / 64, Z), dim3(64), 0, h->stream, Mx, ldm, B, H, W, ldw,
                        nw, ones, h->crow, h->cpart);
-    hipLaunchKernelGGL(k_colsum_final, dim3((K * H + 63) / 64), dim3(256), 0, h->stream, h->cpart, Z, K * H, out);
+    hipLaunchKernelGGL(k_colsum_final, dim3((K * H + 15) / 16), dim3(256), 0, h->stream, h->cpart, Z, K * H, out);
 }
 
 // forward pass of B rows (B a multiple of 64) already in xb; y written
