@@ -147,8 +147,8 @@ __device__ void sweep_tile(const Inst& I, const Tile& tile, char* smem)
         const int slot = slot0 + lane;
         int b = I.bin[slot] - lo + kPad;                         // padded bin index
         uint32_t hc = lH[(b << lnw) + lane];
-        double bc = lbase[b];
-        double lngc = __builtin_fma((double)hc, scale, bc);
+        double lngc = __builtin_fma((double)hc, scale, lbase[b]);
+        const double incv = inc ? scale : 0.0;
 
         // one flip attempt with the precomputed draw (pk, vb) of attempt j;
         // lH always holds the walker's current counts, including bin b
@@ -210,9 +210,11 @@ __device__ void sweep_tile(const Inst& I, const Tile& tile, char* smem)
             const uint32_t hn = lH[(nb << lnw) + lane];
             const double lngn = __builtin_fma((double)hn, scale, bn);   // +inf in a pad
             const double delta = lngc - lngn;                    // exact (or -inf)
-            int f = decide_fast(delta, vb);
-            if (__builtin_expect(__any(f == 2), 0)) {
-                if (f == 2) f = slow_decide(I, T0 + (uint64_t)j, (uint32_t)slot, delta) ? 1 : 0;
+            // delta > vb accepts for certain; below vb - 2 band rejects for certain
+            bool f = delta > vb;
+            const bool band = !f && delta >= vb - 2.0 * kBand;
+            if (__builtin_expect(__any(band), 0)) {
+                if (band) f = slow_decide(I, T0 + (uint64_t)j, (uint32_t)slot, delta);
             }
             if (f) {
                 if (MODEL == 0) ((uint64_t*)latp)[waddr] = wnew;
@@ -220,9 +222,8 @@ __device__ void sweep_tile(const Inst& I, const Tile& tile, char* smem)
             }
             b = f ? nb : b;
             hc = (f ? hn : hc) + inc;
-            bc = f ? bn : bc;
             lH[(b << lnw) + lane] = hc;
-            lngc = __builtin_fma((double)hc, scale, bc);
+            lngc = (f ? lngn : lngc) + incv;                     // exact: base + 2^-k H
         };
 
         // the walker's draws arrive in register chunks of kChunk attempts; the
