@@ -268,6 +268,67 @@ def mlp_bench(rw, args) -> dict:
             "gemm_flops_per_step": flops, "last_loss": loss}
 
 
+def balanced_study(rw, args) -> dict:
+    """Windows of equal width against windows balanced by a pilot run (Sec. V:
+    windows that converge at a similar pace).  The pilot runs the equal layout
+    until every window has halved ln f k_pilot times; a window's difficulty is
+    sqrt(intervals per halving over the pilot's second half) spread over its bins,
+    and rewl_balanced_layout gives windows of equal total difficulty.  Then both
+    layouts run to ln f = 2^-kfinal on the same seed."""
+    from paper_1407_5140_amd import warm as Wm
+    kw = dict(model="ising", q=2, L=args.study_L_balanced, n_windows=8, m=16, kfinal=args.kfinal_balanced,
+              X=10000, seed=1)
+    log = lambda m: print(f"[balanced] {m}", file=sys.stderr, flush=True)
+    cfg = rw.make_config(**kw)
+    W, WB, lo, hi = rw.rewl_layout(cfg)
+    h, kp = kw["n_windows"], args.k_pilot
+    g = rw.Rewl([rw.make_config(**dict(kw, kfinal=kp))], tune=rw.make_tune(poll_every=20))
+    reached = np.full((h, kp + 1), -1, np.int64)
+    t0 = time.perf_counter()
+    while True:
+        done = g.run(20)
+        st = g.state()
+        for a in range(h):
+            for kk in range(int(st["k"][a]) + 1):
+                if reached[a, kk] < 0:
+                    reached[a, kk] = st["t"]
+        if done or time.perf_counter() - t0 > args.max_seconds:
+            break
+    g.close()
+    t_pilot = time.perf_counter() - t0
+    half = kp // 2
+    per = (reached[:, kp] - reached[:, half]) / (kp - half)
+    rho_w = np.sqrt(np.maximum(per, 1.0)) / (hi - lo + 1)
+    rho = np.zeros(W)
+    cnt = np.zeros(W)
+    for a in range(h):
+        rho[lo[a]:hi[a] + 1] += rho_w[a]
+        cnt[lo[a]:hi[a] + 1] += 1
+    rho /= cnt
+    blo, bhi = rw.rewl_balanced_layout(cfg, rho)
+    log(f"pilot {t_pilot:.1f} s, intervals per halving by window {per.tolist()}; balanced windows "
+        f"{list(zip(blo.tolist(), bhi.tolist()))}")
+    ex = exact_ln_g(kw)
+    out = {"mode": "equal against balanced windows", "workload": f"Ising L={kw['L']} h=8 m=16, ln f -> "
+           f"2^-{kw['kfinal']}", "pilot": {"k_pilot": kp, "seconds": t_pilot,
+           "intervals_per_halving": per.tolist()}, "balanced_windows": [blo.tolist(), bhi.tolist()]}
+    for name, wins in (("equal", None), ("balanced", (blo, bhi))):
+        gg, res = Wm.run_to_convergence([dict(kw, windows=wins) if wins is not None else kw],
+                                        args.target_seconds, log=log)
+        r = dict(res[0])
+        if r["converged"] and ex is not None:
+            lng, _ = gg.concat(0)
+            okb = np.isfinite(ex)
+            eps = np.abs(lng[okb] - ex[okb]) / np.abs(ex[okb])
+            r.update(eps_max=float(eps.max()), eps_mean=float(eps.mean()))
+        gg.close()
+        out[name] = r
+        log(f"{name}: {r}")
+    if out["equal"]["converged"] and out["balanced"]["converged"]:
+        out["speedup"] = out["equal"]["seconds"] / out["balanced"]["seconds"]
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -294,6 +355,11 @@ def main(argv=None):
     ap.add_argument("--kfinal-override", type=int, default=0, help="--converge: final ln f exponent")
     ap.add_argument("--mlp-bench", action="store_true", help="time the DOS network's training steps")
     ap.add_argument("--mlp-warmup-steps", type=int, default=20)
+    ap.add_argument("--balanced-study", action="store_true",
+                    help="time to converge with equal windows against pilot-balanced windows")
+    ap.add_argument("--study-L-balanced", type=int, default=32)
+    ap.add_argument("--kfinal-balanced", type=int, default=20)
+    ap.add_argument("--k-pilot", type=int, default=12)
     ap.add_argument("--exchange-study", action="store_true",
                     help="attempts to converge with replica exchange on/off and several intervals")
     ap.add_argument("--study-L", type=int, default=24)
@@ -340,6 +406,9 @@ def main(argv=None):
         return 0
     if args.exchange_study:
         print(json.dumps(exchange_study(rw, args)), flush=True)
+        return 0
+    if args.balanced_study:
+        print(json.dumps(balanced_study(rw, args)), flush=True)
         return 0
     kws = workload(args.workload)
     label = LABELS[args.workload]

@@ -58,6 +58,13 @@ typedef struct {
     uint64_t seed;              /* Philox4x32-10 key                                     */
     int32_t flat_rule;          /* REWL_FLAT_MEAN or REWL_FLAT_VISITS (below)            */
     int32_t reserved;           /* must be 0                                             */
+    const int32_t* window_lo;   /* optional explicit windows, host arrays of n_windows   */
+    const int32_t* window_hi;   /* inclusive global bins (NULL, NULL: the equal-width
+                                   partition of rewl_layout).  Unequal widths let windows
+                                   that converge slowly be narrower (Sec. V).  Rules:
+                                   lo[0] = 0, hi[h-1] = W-1, hi[a] - lo[a] >= 1, both
+                                   ascending strictly, lo[a+1] <= hi[a] (overlap); read
+                                   only during the call that takes the config.          */
 } rewl_config;
 
 /* Flatness rules, tested per walker over the levels of its window that occur;
@@ -91,12 +98,24 @@ typedef struct {
 
 typedef struct rewl_handle rewl_handle;
 
-/* Pure host: global bin count W, bins per window WB, and the window bounds
- * lo[h], hi[h] (inclusive global bins) of Sec. II.A's partition: equal widths,
- * overlap >= o up to one bin, first window starts at bin 0, last ends at W-1.
- * lo/hi may be NULL.  Returns REWL_E_INVALID for a bad configuration.            */
+/* Pure host: global bin count W, bins per window WB (the widest window: every
+ * per-window table has WB entries, index = global bin - lo), and the window
+ * bounds lo[h], hi[h] (inclusive global bins): the explicit windows of the
+ * config if it has them, else Sec. II.A's partition: equal widths, overlap >= o
+ * up to one bin, first window starts at bin 0, last ends at W-1.  lo/hi may be
+ * NULL.  Returns REWL_E_INVALID for a bad configuration.                          */
 rewl_status rewl_layout(const rewl_config* cfg, int32_t* n_bins, int32_t* window_bins,
                         int32_t* lo, int32_t* hi);
+
+/* Pure host: windows of unequal width with equal total difficulty (Sec. V:
+ * windows that converge at a similar pace).  rho[W] > 0 is a per-bin
+ * difficulty density (for instance from a pilot run: sqrt(time per ln f halving)
+ * of a window spread over its bins); with C the cumulative sum of rho, window a
+ * covers C in [a s, a s + l], l = C_total / (1 + (h-1)(1-o)), s = l (1-o), o the
+ * config's overlap, then each window is widened as needed to at least 2 bins and
+ * an overlap of at least 8 bins (enough for the Sec. II.B joins).  lo[h], hi[h]
+ * receive inclusive global bins valid as the config's explicit windows.          */
+rewl_status rewl_balanced_layout(const rewl_config* cfg, const double* rho, int32_t* lo, int32_t* hi);
 
 /* Pure host: mask[W] = 1 where the energy level occurs on the periodic lattice. */
 rewl_status rewl_mask(const rewl_config* cfg, uint8_t* mask);

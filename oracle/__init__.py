@@ -41,16 +41,26 @@ class Config(ctypes.Structure):
                 ("flat_num", ctypes.c_int32), ("flat_den", ctypes.c_int32),
                 ("lnf_k0", ctypes.c_int32), ("lnf_kfinal", ctypes.c_int32),
                 ("exchange_enabled", ctypes.c_int32), ("exchange_interval", ctypes.c_int64),
-                ("seed", ctypes.c_uint64), ("flat_rule", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("seed", ctypes.c_uint64), ("flat_rule", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("window_lo", ctypes.c_void_p), ("window_hi", ctypes.c_void_p)]
 
 
 def make_config(model="ising", q=2, L=8, n_windows=4, overlap=(3, 4), m=1, flat=(4, 5),
-                k0=0, kfinal=20, X=10000, seed=1, exchange=True, flat_rule="mean") -> Config:
+                k0=0, kfinal=20, X=10000, seed=1, exchange=True, flat_rule="mean",
+                windows=None) -> Config:
     """flat_rule "mean": min H >= num/den of the mean (Sec. II.A); "visits":
-    H(E) >= (num/den)/sqrt(ln f) for every E, Eq. (8)."""
-    return Config(0 if model == "ising" else 1, q, L, n_windows, overlap[0], overlap[1], m,
-                  flat[0], flat[1], k0, kfinal, 1 if exchange else 0, X, seed,
-                  {"mean": 0, "visits": 1}[flat_rule], 0)
+    H(E) >= (num/den)/sqrt(ln f) for every E, Eq. (8).  windows: optional
+    (lo, hi) sequences of inclusive global bins (unequal widths); the config
+    keeps the arrays alive."""
+    c = Config(0 if model == "ising" else 1, q, L, n_windows, overlap[0], overlap[1], m,
+               flat[0], flat[1], k0, kfinal, 1 if exchange else 0, X, seed,
+               {"mean": 0, "visits": 1}[flat_rule], 0, None, None)
+    if windows is not None:
+        c._wlo = np.ascontiguousarray(windows[0], dtype=np.int32)
+        c._whi = np.ascontiguousarray(windows[1], dtype=np.int32)
+        c.window_lo = c._wlo.ctypes.data
+        c.window_hi = c._whi.ctypes.data
+    return c
 
 
 def lib():

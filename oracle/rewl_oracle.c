@@ -152,6 +152,18 @@ int orc_layout(const orc_config* c, int32_t* lo, int32_t* hi)
 {
     int64_t S = orc_n_bins(c) - 1;
     int64_t h = c->n_windows, num = c->overlap_num, den = c->overlap_den;
+    if (c->window_lo || c->window_hi) {
+        /* explicit windows (unequal widths, Sec. V): each at least 2 bins, both  */
+        /* ends ascending, covering [0, S], each overlapping the next             */
+        if (!c->window_lo || !c->window_hi || h < 1) return -1;
+        for (int64_t a = 0; a < h; ++a) {
+            lo[a] = c->window_lo[a];
+            hi[a] = c->window_hi[a];
+            if (lo[a] < 0 || hi[a] > S || hi[a] - lo[a] < 1) return -1;
+            if (a > 0 && (lo[a] <= lo[a - 1] || hi[a] <= hi[a - 1] || lo[a] > hi[a - 1])) return -1;
+        }
+        return (lo[0] == 0 && hi[h - 1] == S) ? 0 : -1;
+    }
     if (h < 1 || den < 1 || num < 0 || num >= den) return -1;
     if (h == 1) {
         lo[0] = 0;
@@ -299,7 +311,9 @@ orc_sim* orc_create(const orc_config* c, const uint8_t* mask, const double* init
         orc_destroy(s);
         return NULL;
     }
-    s->WB = s->hi[0] - s->lo[0] + 1;
+    s->WB = 0;                          /* table length: the widest window */
+    for (int a = 0; a < s->h; ++a)
+        if (s->hi[a] - s->lo[a] + 1 > s->WB) s->WB = s->hi[a] - s->lo[a] + 1;
     s->mask = malloc(s->W);
     if (mask)
         memcpy(s->mask, mask, s->W);
@@ -330,7 +344,8 @@ orc_sim* orc_create(const orc_config* c, const uint8_t* mask, const double* init
     for (int sl = 0; sl < s->S; ++sl) {
         int a = sl / s->m;
         for (int b = 0; b < s->WB; ++b)
-            s->lng[(size_t)sl * s->WB + b] = init_lng ? init_lng[s->lo[a] + b] : 0.0;
+            s->lng[(size_t)sl * s->WB + b] =
+                (init_lng && s->lo[a] + b <= s->hi[a]) ? init_lng[s->lo[a] + b] : 0.0;
     }
     int stuck = 0, imax = 0;
     /* walkers are independent: each drives only its own lattice */
@@ -435,7 +450,7 @@ static int merge_window(orc_sim* s, int a)
         if ((__float128)mean[b] != mq) { free(mean); return -5; }   /* budget exceeded */
     }
     double mn = INFINITY;
-    for (int b = 0; b < WB; ++b)
+    for (int b = 0; b <= s->hi[a] - s->lo[a]; ++b)
         if (s->mask[s->lo[a] + b] && mean[b] < mn) mn = mean[b];
     double shift = floor(mn);
     for (int b = 0; b < WB; ++b) {
@@ -597,7 +612,9 @@ int orc_concat(const orc_config* c, const uint8_t* mask, const double* pieces, d
     int32_t* lo = malloc(h * sizeof(int32_t));
     int32_t* hi = malloc(h * sizeof(int32_t));
     if (orc_layout(c, lo, hi) != 0) { free(lo); free(hi); return -1; }
-    int WB = hi[0] - lo[0] + 1;
+    int WB = 0;
+    for (int a = 0; a < h; ++a)
+        if (hi[a] - lo[a] + 1 > WB) WB = hi[a] - lo[a] + 1;
     double* shift = calloc(h, sizeof(double));
     int rc = 0;
     for (int a = 0; a + 1 < h; ++a) {

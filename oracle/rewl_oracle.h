@@ -39,6 +39,8 @@ typedef struct {
     int32_t flat_rule;          /* 0: min H >= num/den mean H (Sec. II.A);
                                    1: H(E) >= (num/den)/sqrt(ln f) for all E, Eq. (8)   */
     int32_t reserved;
+    const int32_t* window_lo;   /* optional explicit windows (inclusive global bins,     */
+    const int32_t* window_hi;   /* n_windows each); NULL: the equal-width partition      */
 } orc_config;
 
 typedef struct orc_sim orc_sim;

@@ -40,7 +40,8 @@ class rewl_config(ctypes.Structure):
                 ("flat_num", ctypes.c_int32), ("flat_den", ctypes.c_int32),
                 ("lnf_k0", ctypes.c_int32), ("lnf_kfinal", ctypes.c_int32),
                 ("exchange_enabled", ctypes.c_int32), ("exchange_interval", ctypes.c_int64),
-                ("seed", ctypes.c_uint64), ("flat_rule", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("seed", ctypes.c_uint64), ("flat_rule", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("window_lo", ctypes.c_void_p), ("window_hi", ctypes.c_void_p)]
 
 
 REWL_SWEEP_AUTO, REWL_SWEEP_LANE, REWL_SWEEP_WAVE = 0, 1, 2
@@ -70,6 +71,7 @@ _sigs = {
     "rewl_last_error": ([], ctypes.c_char_p),
     "rewl_layout": ([_P(rewl_config), _vp, _vp, _vp, _vp], ctypes.c_int),
     "rewl_mask": ([_P(rewl_config), _vp], ctypes.c_int),
+    "rewl_balanced_layout": ([_P(rewl_config), _vp, _vp, _vp], ctypes.c_int),
     "rewl_create": ([_P(rewl_config), _vp, _P(_vp)], ctypes.c_int),
     "rewl_batch_create": ([_P(rewl_config), ctypes.c_int32, _vp, _P(rewl_tune), _P(_vp)], ctypes.c_int),
     "rewl_set_initial_lng": ([_vp, ctypes.c_int32, _vp], ctypes.c_int),
@@ -134,14 +136,22 @@ REWL_FLAT_MEAN, REWL_FLAT_VISITS = 0, 1
 
 
 def make_config(model="ising", q=2, L=8, n_windows=4, overlap=(3, 4), m=1, flat=(4, 5), k0=0,
-                kfinal=20, X=10000, seed=1, exchange=True, flat_rule="mean") -> rewl_config:
+                kfinal=20, X=10000, seed=1, exchange=True, flat_rule="mean", windows=None) -> rewl_config:
     """Problem statement of Sec. II.A / IV: model, L, h windows with overlap o,
     m walkers per window, flatness num/den (rule "mean": min H >= num/den of the
     mean; rule "visits": H >= (num/den)/sqrt(ln f), Eq. (8)), ln f = 2^-k0 ..
-    2^-kfinal, X attempts per walker between exchanges, Philox seed."""
-    return rewl_config(0 if model == "ising" else 1, q, L, n_windows, overlap[0], overlap[1], m,
-                       flat[0], flat[1], k0, kfinal, 1 if exchange else 0, X, seed,
-                       {"mean": REWL_FLAT_MEAN, "visits": REWL_FLAT_VISITS}[flat_rule], 0)
+    2^-kfinal, X attempts per walker between exchanges, Philox seed; windows:
+    optional (lo, hi) inclusive global bins of unequal windows (kept alive by
+    the returned config)."""
+    c = rewl_config(0 if model == "ising" else 1, q, L, n_windows, overlap[0], overlap[1], m,
+                    flat[0], flat[1], k0, kfinal, 1 if exchange else 0, X, seed,
+                    {"mean": REWL_FLAT_MEAN, "visits": REWL_FLAT_VISITS}[flat_rule], 0, None, None)
+    if windows is not None:
+        c._wlo = np.ascontiguousarray(windows[0], dtype=np.int32)
+        c._whi = np.ascontiguousarray(windows[1], dtype=np.int32)
+        c.window_lo = c._wlo.ctypes.data
+        c.window_hi = c._whi.ctypes.data
+    return c
 
 
 # ------------------------------------------------------------ C-ABI mirrors
@@ -152,6 +162,15 @@ def rewl_layout(cfg: rewl_config):
     _check(_lib.rewl_layout(ctypes.byref(cfg), ctypes.byref(nb), ctypes.byref(wb), _p(lo), _p(hi)),
            "rewl_layout")
     return nb.value, wb.value, lo, hi
+
+
+def rewl_balanced_layout(cfg: rewl_config, rho) -> tuple[np.ndarray, np.ndarray]:
+    """Unequal windows of equal total difficulty rho[W] (pure host)."""
+    r = np.ascontiguousarray(rho, dtype=np.float64)
+    lo = np.zeros(cfg.n_windows, np.int32)
+    hi = np.zeros(cfg.n_windows, np.int32)
+    _check(_lib.rewl_balanced_layout(ctypes.byref(cfg), _p(r), _p(lo), _p(hi)), "rewl_balanced_layout")
+    return lo, hi
 
 
 def rewl_mask(cfg: rewl_config) -> np.ndarray:

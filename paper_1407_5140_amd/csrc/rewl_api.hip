@@ -52,6 +52,16 @@ int64_t n_bins_of(const rewl_config& c)
 bool layout_of(const rewl_config& c, std::vector<int32_t>& lo, std::vector<int32_t>& hi)
 {
     const int64_t S = n_bins_of(c) - 1, h = c.n_windows, num = c.overlap_num, den = c.overlap_den;
+    if (c.window_lo || c.window_hi) {
+        if (!c.window_lo || !c.window_hi || h < 1) return false;
+        lo.assign(c.window_lo, c.window_lo + h);
+        hi.assign(c.window_hi, c.window_hi + h);
+        for (int64_t a = 0; a < h; ++a) {
+            if (lo[a] < 0 || hi[a] > S || hi[a] - lo[a] < 1) return false;
+            if (a > 0 && (lo[a] <= lo[a - 1] || hi[a] <= hi[a - 1] || lo[a] > hi[a - 1])) return false;
+        }
+        return lo[0] == 0 && hi[h - 1] == S;
+    }
     if (h < 1 || den < 1 || num < 0 || num >= den) return false;
     lo.assign(h, 0);
     hi.assign(h, 0);
@@ -301,9 +311,68 @@ rewl_status rewl_layout(const rewl_config* cfg, int32_t* n_bins, int32_t* window
     std::vector<int32_t> l, u;
     layout_of(*cfg, l, u);
     if (n_bins) *n_bins = (int32_t)n_bins_of(*cfg);
-    if (window_bins) *window_bins = u[0] - l[0] + 1;
+    if (window_bins) {
+        int32_t wb = 0;
+        for (size_t a = 0; a < l.size(); ++a) wb = std::max(wb, u[a] - l[a] + 1);
+        *window_bins = wb;
+    }
     if (lo) std::copy(l.begin(), l.end(), lo);
     if (hi) std::copy(u.begin(), u.end(), hi);
+    return REWL_OK;
+}
+
+rewl_status rewl_balanced_layout(const rewl_config* cfg, const double* rho, int32_t* lo, int32_t* hi)
+{
+    if (!cfg || !rho || !lo || !hi) return fail(REWL_E_INVALID, "null argument");
+    rewl_config c = *cfg;
+    c.window_lo = c.window_hi = nullptr;
+    rewl_status st = validate(c);
+    if (st != REWL_OK) return st;
+    const int64_t W = n_bins_of(c), h = c.n_windows;
+    std::vector<double> C(W);
+    double acc = 0.0;
+    for (int64_t b = 0; b < W; ++b) {
+        if (!(rho[b] > 0.0) || !std::isfinite(rho[b])) return fail(REWL_E_INVALID, "rho must be finite and > 0");
+        acc += rho[b];
+        C[b] = acc;                                   // C[b] = sum of rho over bins <= b
+    }
+    std::vector<int32_t> l(h), u(h);
+    if (h == 1) {
+        l[0] = 0;
+        u[0] = (int32_t)(W - 1);
+    } else {
+        const double o = (double)c.overlap_num / c.overlap_den;
+        const double span = acc / (1.0 + (double)(h - 1) * (1.0 - o)), step = span * (1.0 - o);
+        auto first_at = [&](double v) {               // first bin whose cumulative sum reaches v
+            return (int32_t)(std::lower_bound(C.begin(), C.end(), v) - C.begin());
+        };
+        for (int64_t a = 0; a < h; ++a) {
+            l[a] = a == 0 ? 0 : std::min<int32_t>(first_at(a * step), (int32_t)(W - 1));
+            u[a] = a == h - 1 ? (int32_t)(W - 1) : std::min<int32_t>(first_at(a * step + span), (int32_t)(W - 1));
+        }
+        // minimum sizes: 2 bins per window, 8 bins of overlap, both ends ascending
+        const int32_t kMinOverlap = 8;
+        for (int64_t a = 0; a < h; ++a) {
+            if (a > 0) l[a] = std::max(l[a], l[a - 1] + 1);
+            u[a] = std::max(u[a], l[a] + 1);
+            if (a > 0) u[a] = std::max(u[a], u[a - 1] + 1);
+        }
+        for (int64_t a = 0; a + 1 < h; ++a)
+            if (u[a] - l[a + 1] + 1 < kMinOverlap) {
+                const int32_t need = kMinOverlap - (u[a] - l[a + 1] + 1);
+                const int32_t down = std::min<int32_t>(need / 2 + need % 2, l[a + 1] - l[a] - 1);
+                l[a + 1] -= std::max(down, 0);
+                u[a] = std::min<int32_t>(u[a] + (need - std::max(down, 0)), (int32_t)(W - 1));
+            }
+        for (int64_t a = 1; a < h; ++a) u[a] = std::max(u[a], u[a - 1] + 1);
+        u[h - 1] = (int32_t)(W - 1);
+    }
+    c.window_lo = l.data();
+    c.window_hi = u.data();
+    st = validate(c);
+    if (st != REWL_OK) return fail(st, "no valid unequal layout for these sizes: " + std::string(rewl_last_error()));
+    std::copy(l.begin(), l.end(), lo);
+    std::copy(u.begin(), u.end(), hi);
     return REWL_OK;
 }
 
@@ -382,7 +451,8 @@ static rewl_status create_impl(const rewl_config* cfgs, int32_t n, void* hip_str
         hi.wpr = c.model == 0 ? (c.L + 63) / 64 : 1;
         layout_of(c, hi.lo, hi.hi);
         mask_of(c, hi.mask);
-        hi.WB = hi.hi[0] - hi.lo[0] + 1;
+        hi.WB = 0;                                          // the widest window
+        for (int a = 0; a < hi.h; ++a) hi.WB = std::max(hi.WB, hi.hi[a] - hi.lo[a] + 1);
         hi.nreach.assign(hi.h, 0);
         for (int a = 0; a < hi.h; ++a)
             for (int b = hi.lo[a]; b <= hi.hi[a]; ++b) hi.nreach[a] += hi.mask[b];
@@ -626,7 +696,8 @@ rewl_status rewl_set_initial_lng(rewl_handle* H, int32_t i, const double* lng)
     }
     std::vector<double> tab((size_t)hi.h * hi.WB);
     for (int a = 0; a < hi.h; ++a)
-        for (int b = 0; b < hi.WB; ++b) tab[(size_t)a * hi.WB + b] = lng[hi.lo[a] + b];
+        for (int b = 0; b < hi.WB; ++b)
+            tab[(size_t)a * hi.WB + b] = hi.lo[a] + b <= hi.hi[a] ? lng[hi.lo[a] + b] : 0.0;
     HIP_TRY(hipMemcpyAsync(hi.dev.base, tab.data(), tab.size() * 8, hipMemcpyHostToDevice, H->stream));
     HIP_TRY(hipStreamSynchronize(H->stream));
     return REWL_OK;

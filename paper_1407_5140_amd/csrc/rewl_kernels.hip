@@ -111,9 +111,12 @@ __device__ void sweep_tile(const Inst& I, const Tile& tile, char* smem)
     // ---- stage the window table, the tile's histograms and lattices in LDS;
     //      levels that never occur carry the sentinel 0xffffffff (never visited,
     //      excluded from the flatness minimum, written back as 0)
+    // bins b >= width (a window narrower than WB) are outside the window: +inf
+    // table (moves there are rejected) and the never-visited sentinel
+    const int width = I.hi[a] - lo + 1;
     for (int i = lane; i < nbins; i += nthr) {
         const int b = i - kPad;
-        lbase[i] = (b >= 0 && b < WB) ? I.base[(size_t)a * WB + b] : __builtin_inf();
+        lbase[i] = (b >= 0 && b < width) ? I.base[(size_t)a * WB + b] : __builtin_inf();
     }
     // global H is walker-major: H[slot][bin]; consecutive threads take consecutive bins
     for (int l = 0; l < nw; ++l)
@@ -121,7 +124,7 @@ __device__ void sweep_tile(const Inst& I, const Tile& tile, char* smem)
             const int b = i - kPad;
             uint32_t hv = 0;
             if (b >= 0 && b < WB)
-                hv = I.mask[lo + b] ? I.H[(size_t)(slot0 + l) * WB + b] : 0xffffffffu;
+                hv = (b < width && I.mask[lo + b]) ? I.H[(size_t)(slot0 + l) * WB + b] : 0xffffffffu;
             lH[(i << lnw) + l] = hv;
         }
     // lattices are walker-major too: lat[slot][word] / plat[slot][site]
@@ -389,9 +392,11 @@ __device__ void sweep_wave(const Inst& I, const Tile& tile, char* smem)
     const int nbins = WB + 2 * kPad;
     const int lo = I.lo[a];
     double* lbase = (double*)smem;
+    // bins b >= width (a window narrower than WB) lie outside the window
+    const int width = I.hi[a] - lo + 1;
     for (int i = threadIdx.x; i < nbins; i += blockDim.x) {
         const int b = i - kPad;
-        lbase[i] = (b >= 0 && b < WB) ? I.base[(size_t)a * WB + b] : __builtin_inf();
+        lbase[i] = (b >= 0 && b < width) ? I.base[(size_t)a * WB + b] : __builtin_inf();
     }
     const bool active = wave < G;
     const int r = tile.r0 + wave, slot = a * I.m + r;
@@ -405,7 +410,7 @@ __device__ void sweep_wave(const Inst& I, const Tile& tile, char* smem)
             const int b = i - kPad;
             uint32_t hv = 0;
             if (b >= 0 && b < WB)
-                hv = I.mask[lo + b] ? I.H[(size_t)slot * WB + b] : 0xffffffffu;
+                hv = (b < width && I.mask[lo + b]) ? I.H[(size_t)slot * WB + b] : 0xffffffffu;
             lH[i] = hv;
         }
         for (int i = lane; i < N; i += 64) lmap[i] = 0;
@@ -640,7 +645,7 @@ __global__ void __launch_bounds__(256) k_merge(const Inst* __restrict__ insts,
         for (int r = 0; r < m; ++r) s += H[(size_t)r * WB + b];
         const double nb = base[b] + __builtin_ldexp((double)s, -sh);
         base[b] = nb;
-        if (I.mask[lo + b]) mn = nb < mn ? nb : mn;
+        if (b <= I.hi[a] - lo && I.mask[lo + b]) mn = nb < mn ? nb : mn;
         mx = fabs(nb) > mx ? fabs(nb) : mx;
     }
     red[tid] = mn;

@@ -76,3 +76,38 @@ def test_invalid_configs_rejected_before_allocation(rw, kw, status):
     assert e.value.status == status
     with pytest.raises(rw.RewlError):
         rw.rewl_layout(c)
+
+
+def test_explicit_windows_layout_matches_oracle(rw):
+    import oracle as O
+    wins = ([0, 12, 26, 44], [20, 38, 52, 64])
+    c = rw.make_config("ising", L=8, n_windows=4, windows=wins)
+    oc = O.make_config("ising", L=8, n_windows=4, windows=wins)
+    W, WB, lo, hi = rw.rewl_layout(c)
+    olo, ohi = O.layout(oc)
+    assert W == 65 and WB == 27 and np.array_equal(lo, olo) and np.array_equal(hi, ohi)
+    for bad in (([0, 25, 30], [20, 40, 64]), ([0, 10, 30], [20, 40, 63]), ([0, 10, 30], [20, 40, 30])):
+        with pytest.raises(rw.RewlError):
+            rw.rewl_layout(rw.make_config("ising", L=8, n_windows=3, windows=bad))
+
+
+@pytest.mark.parametrize("model,q,L,h", [("ising", 2, 32, 8), ("potts", 10, 24, 12), ("ising", 2, 64, 16)])
+def test_balanced_layout_equalises_difficulty(rw, model, q, L, h):
+    c = rw.make_config(model, q=q, L=L, n_windows=h)
+    W, WB, lo_eq, hi_eq = rw.rewl_layout(c)
+    # uniform difficulty gives back the equal partition up to rounding
+    lo, hi = rw.rewl_balanced_layout(c, np.ones(W))
+    assert np.abs(lo - lo_eq).max() <= 2 and np.abs(hi - hi_eq).max() <= 2
+    # harder ends: narrower end windows, sums of rho about equal, a valid layout
+    rho = np.ones(W)
+    rho[: W // 5] = 4.0
+    rho[-(W // 5):] = 4.0
+    lo, hi = rw.rewl_balanced_layout(c, rho)
+    c2 = rw.make_config(model, q=q, L=L, n_windows=h, windows=(lo, hi))
+    W2, WB2, lo2, hi2 = rw.rewl_layout(c2)
+    assert np.array_equal(lo2, lo) and np.array_equal(hi2, hi) and WB2 == (hi - lo + 1).max()
+    width = hi - lo + 1
+    assert width[0] < width[h // 2] and width[-1] < width[h // 2]
+    sums = np.array([rho[l:u + 1].sum() for l, u in zip(lo, hi)])
+    assert sums.max() / sums.min() < 1.25
+    assert ((hi[:-1] - lo[1:] + 1) >= 8).all()

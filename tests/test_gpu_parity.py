@@ -106,6 +106,11 @@ SMALL = [
     # Eq. (8): every level visited at least a / sqrt(ln f) times by every walker
     dict(model="ising", L=16, n_windows=4, m=8, kfinal=12, X=3000, seed=31, flat_rule="visits", flat=(1, 1)),
     dict(model="potts", q=10, L=8, n_windows=4, m=4, kfinal=12, X=3000, seed=37, flat_rule="visits", flat=(3, 2)),
+    # explicit windows of unequal width (narrower tables padded to the widest)
+    dict(model="ising", L=16, n_windows=4, m=8, kfinal=12, X=3000, seed=41,
+         windows=([0, 30, 70, 110], [50, 100, 140, 256])),
+    dict(model="potts", q=10, L=8, n_windows=4, m=4, kfinal=12, X=3000, seed=43,
+         windows=([0, 20, 50, 80], [40, 70, 100, 128])),
 ]
 
 
@@ -115,7 +120,8 @@ def _tune(rw, kind, wpb=0, graph=0, poll=8):
 
 @pytest.mark.parametrize("kind", ["lane", "wave"])
 @pytest.mark.parametrize("kw", SMALL, ids=lambda kw: f"{kw['model']}-L{kw['L']}-h{kw['n_windows']}-m{kw['m']}"
-                                                   f"{'-' + kw['flat_rule'] if 'flat_rule' in kw else ''}")
+                                                   f"{'-' + kw['flat_rule'] if 'flat_rule' in kw else ''}"
+                                                   f"{'-windows' if 'windows' in kw else ''}")
 def test_lockstep_small(rw, kw, kind):
     steps = 40 if kw["X"] > 1 else 3000
     gpu, _, _ = _lockstep(rw, kw, steps, tune=_tune(rw, kind), every=1 if kw["X"] > 1 else 500)

@@ -424,3 +424,27 @@ def test_visits_rule_with_a_zero_merges_every_interval():
         done = sim.run(1)
         assert list(sim.state()["k"]) == [2 + t] * 3
         assert done == (t == 7)
+
+
+# ------------------------------------------------------------ unequal windows
+def test_unequal_windows_converge_to_exact_ising_L8(golden):
+    """Explicit windows of different widths (narrow at the ends) through the whole
+    method: sweep, merge, exchange and the Sec. II.B joins."""
+    exact = X.ln_g(golden.counts("ising_q2_L8_counts.txt"))
+    c = O.make_config("ising", L=8, n_windows=4, m=16, kfinal=20, seed=3,
+                      windows=([0, 12, 26, 44], [20, 38, 52, 64]))
+    sim = O.Sim(c)
+    assert sim.WB == 27
+    assert sim.run(100000)
+    err = _concat_error(sim, exact)
+    assert err.max() < 0.08
+
+
+@pytest.mark.parametrize("lo,hi", [([0, 25, 30], [20, 40, 64]),     # gap between windows 0 and 1
+                                   ([0, 10, 30], [20, 40, 63]),     # does not reach the top
+                                   ([1, 10, 30], [20, 40, 64]),     # does not start at 0
+                                   ([0, 10, 10], [20, 40, 64]),     # starts not ascending
+                                   ([0, 10, 30], [20, 40, 30])])    # a one-bin window
+def test_bad_explicit_windows_rejected(lo, hi):
+    with pytest.raises(ValueError):
+        O.Sim(O.make_config("ising", L=8, n_windows=3, windows=(lo, hi)))
