@@ -42,6 +42,7 @@ LABELS = {
     "ising32": "2D Ising L=32 periodic, 8 windows o=3/4, 16 walkers/window, X=1e4, ln f to 2^-20",
     "ising64": "2D Ising L=64 periodic, 16 windows o=3/4, 64 walkers/window, X=1e4",
     "potts32": "2D 10-state Potts L=32 periodic, 32 windows o=3/4, 128 walkers/window, X=1e4",
+    "potts100": "2D 10-state Potts L=100 periodic, 77 windows of 1001 bins o=3/4, 8 walkers/window, X=1e4",
     "batch64": "64 independent REWL instances: Ising L 16-64 and Potts q 4/8/10 L 16-32, "
                "8-32 windows, 32-128 walkers/window, X=1e4",
 }
@@ -329,6 +330,64 @@ def balanced_study(rw, args) -> dict:
     return out
 
 
+def ensemble_study(rw, args) -> dict:
+    """The paper's 10-state Potts L=100 workload (77 windows of 1001 bins, overlap
+    3/4, m walkers per window) as n independent runs in one batch, run to
+    ln f = 2^-kfinal or the time limit; then the error analysis of Sec. II.B
+    (mean of the n pieces per window + R bootstrap resamples, rewl_ensemble) and
+    the specific heat of every row (rewl_thermo) near the transition."""
+    from paper_1407_5140_amd import workloads as Wl
+    log = lambda m: print(f"[ensemble] {m}", file=sys.stderr, flush=True)
+    n = args.ens_runs
+    base = dict(Wl.single("potts100"), kfinal=args.ens_kfinal)
+    if args.m:
+        base["m"] = args.m
+    kws = [dict(base, seed=1 + j) for j in range(n)]
+    t0 = time.perf_counter()
+    g = rw.Rewl([rw.make_config(**kw) for kw in kws], tune=rw.make_tune(poll_every=50))
+    t_create = time.perf_counter() - t0
+    info = g.info()
+    log(f"{n} runs x {base['n_windows']} windows x {base['m']} walkers, {info['sweep_kind']} sweep, "
+        f"create {t_create:.1f} s")
+    t0 = time.perf_counter()
+    last = t0
+    done = False
+    while not done and time.perf_counter() - t0 < args.max_seconds:
+        done = g.run(50)
+        if time.perf_counter() - last > 30:
+            last = time.perf_counter()
+            sts = [g.stats(i) for i in range(n)]
+            log(f"{last - t0:.0f} s: intervals {sts[0]['intervals']}, min k "
+                f"{[s['min_k'] for s in sts]}, windows done {[s['windows_done'] for s in sts]}")
+    t_run = time.perf_counter() - t0
+    sts = [g.stats(i) for i in range(n)]
+    attempts = sum(s["attempts"] for s in sts)
+    log(f"run {t_run:.1f} s, {attempts / t_run:.4g} attempts/s, converged {done}")
+    R = args.ens_R
+    t0 = time.perf_counter()
+    rows, joins = g.ensemble(list(range(n)), R=R, seed=1)
+    t_ens = time.perf_counter() - t0
+    g.close()
+    T = np.linspace(args.ens_tmin, args.ens_tmax, args.ens_nT)
+    t0 = time.perf_counter()
+    u, c, f = rw.rewl_thermo("potts", base["L"], rows, T)
+    t_th = time.perf_counter() - t0
+    peak = T[np.argmax(c, axis=1)]
+    cmax = c.max(axis=1)
+    out = {"mode": "n-run ensemble, bootstrap and specific heat",
+           "workload": f"2D 10-state Potts L={base['L']}, {base['n_windows']} windows o=3/4, "
+                       f"m={base['m']}, ln f -> 2^-{base['kfinal']}, {n} runs",
+           "converged": bool(done), "run_seconds": t_run, "attempts_per_s": attempts / t_run,
+           "min_k": [s["min_k"] for s in sts], "intervals": sts[0]["intervals"],
+           "resamples": R, "ensemble_seconds": t_ens, "thermo_seconds": t_th,
+           "thermo_grid": [float(T[0]), float(T[-1]), int(T.size)],
+           "T_peak": float(peak[0]), "T_peak_err": float(np.std(peak[1:])) if R > 1 else None,
+           "c_max": float(cmax[0]), "c_max_err": float(np.std(cmax[1:])) if R > 1 else None,
+           "joins_spread": float(np.mean(np.std(joins[1:], axis=0))) if R > 1 else None}
+    log(json.dumps(out))
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -365,6 +424,14 @@ def main(argv=None):
     ap.add_argument("--study-L", type=int, default=24)
     ap.add_argument("--study-kfinal", type=int, default=14)
     ap.add_argument("--study-seeds", type=int, default=4)
+    ap.add_argument("--ensemble-study", action="store_true",
+                    help="the paper's Potts L=100 workload as n runs + bootstrap + specific heat")
+    ap.add_argument("--ens-runs", type=int, default=4)
+    ap.add_argument("--ens-kfinal", type=int, default=10)
+    ap.add_argument("--ens-R", type=int, default=200)
+    ap.add_argument("--ens-tmin", type=float, default=0.68)
+    ap.add_argument("--ens-tmax", type=float, default=0.74)
+    ap.add_argument("--ens-nT", type=int, default=601)
     ap.add_argument("--warm", action="store_true",
                     help="train the DOS network on REWL results of small systems and compare "
                          "time to converge, warm start against plain REWL, on larger targets")
@@ -406,6 +473,9 @@ def main(argv=None):
         return 0
     if args.exchange_study:
         print(json.dumps(exchange_study(rw, args)), flush=True)
+        return 0
+    if args.ensemble_study:
+        print(json.dumps(ensemble_study(rw, args)), flush=True)
         return 0
     if args.balanced_study:
         print(json.dumps(balanced_study(rw, args)), flush=True)

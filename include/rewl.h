@@ -80,7 +80,8 @@ enum { REWL_FLAT_MEAN = 0, REWL_FLAT_VISITS = 1 };
 /* Sweep variants.  LANE: one walker per lane, draws precomputed for the whole
  * interval by a separate kernel (suits batches of many thousands of walkers).
  * WAVE: one walker per wave, the chain on wave-uniform values, the lanes draw
- * the next 64 attempts (suits few walkers; needs Ising L <= 64, Potts N <= 4096). */
+ * the next 64 attempts (suits few walkers; falls back to LANE where one walker's
+ * wave tables do not fit the LDS).                                               */
 enum { REWL_SWEEP_AUTO = 0, REWL_SWEEP_LANE = 1, REWL_SWEEP_WAVE = 2 };
 
 /* Optional tuning of a batch (NULL = library choice). */
@@ -153,6 +154,38 @@ rewl_status rewl_get_window_lng(rewl_handle* h, int32_t instance, int32_t window
  * a level does not occur), normalised to sum_E g(E) = q^N (Ising: 2^N).  join
  * (h-1 entries, may be NULL) receives the join bins.  Runs on the device.      */
 rewl_status rewl_concat(rewl_handle* h, int32_t instance, double* out_lng, int32_t* join);
+
+/* Error analysis over n independent runs (Sec. II.B).  runs[0..n) are instances
+ * of the handle with equal model, q, L and windows (normally differing only in
+ * seed); each supplies one piece per window, its rewl_get_window_lng table.
+ *   Row 0 of out_lng: the mean global ln g.  For every window, the bin-wise
+ *   mean of the n runs' pieces (summed in run order, then divided by n), then
+ *   the concatenation of rewl_concat.
+ *   Rows 1..R: bootstrap resamples.  For every window, n pieces drawn with
+ *   repetition, then the same mean and concatenation.  Draw j of window a in
+ *   resample r takes run runs[floor(x0 * n / 2^32)], x0 the first word of
+ *   Philox4x32-10 at counter (r, j, a, 4) under key (seed low word, seed high).
+ * The mean is taken over ln g; each run's additive constant only shifts a mean
+ * piece, which the joining removes.  out_lng: (R+1) x W host doubles, row-major;
+ * join (may be NULL): (R+1) x (h-1) host ints.  1 <= n <= 4096, 0 <= R <= 65534,
+ * device tables up to 16 GiB per call (about (R+1)(h WB + W) doubles).
+ * REWL_E_STATE if some overlap of some row has no valid join point (every row
+ * is still written).  Runs on the device; returns with the stream synchronised. */
+rewl_status rewl_ensemble(rewl_handle* h, const int32_t* runs, int32_t n, int32_t R, uint64_t seed,
+                          double* out_lng, int32_t* join);
+
+/* Canonical averages from densities of states (k_B = J = 1), as used for the
+ * specific heat of the Potts study (Sec. IV.A).  For every row s < S of lng
+ * (S x W host doubles over the bins of `model` on the L x L lattice, the
+ * convention above; -inf marks a level that does not occur) and every
+ * temperature T[t] > 0, with Z = sum_E g(E) e^{-E/T}:
+ *   u = <E> / N,  c = <(E - <E>)^2> / (N T^2),  f = -T ln Z / N.
+ * u, c, f: S x nT host doubles, row-major, each may be NULL.  Terms below
+ * e^-745 of the largest are zero (double precision).  REWL_E_INVALID for NaN or
+ * +inf in lng, a row without an occurring level, T <= 0, S outside 1..65535.
+ * Runs on the device (library-owned buffers, the null stream).                */
+rewl_status rewl_thermo(int32_t model, int32_t L, const double* lng, int32_t S, const double* T,
+                        int32_t nT, double* u, double* c, double* f);
 
 /* Full state of one instance for inspection (S = h*m slots, slot = a*m + r):
  *   spins[S*N] (Ising 1 = up; Potts 0..q-1), bins[S], H[S*WB], lng[S*WB]

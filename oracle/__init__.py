@@ -96,6 +96,9 @@ def lib():
         L.orc_concat.argtypes = [P(Config), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                  ctypes.c_void_p]
         L.orc_concat.restype = ctypes.c_int
+        L.orc_boot_picks.argtypes = [ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                     ctypes.c_void_p]
+        L.orc_boot_picks.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -150,6 +153,14 @@ def concat(cfg: Config, mask: np.ndarray, pieces: np.ndarray):
     if rc != 0:
         raise ValueError(f"concatenation failed ({rc})")
     return out, join[: max(cfg.n_windows - 1, 0)]
+
+
+def boot_picks(seed: int, R: int, h: int, n: int) -> np.ndarray:
+    """Run index of every draw, shape (R + 1, h, n); resample 0 is the ensemble itself."""
+    out = np.zeros((R + 1, h, n), dtype=np.int32)
+    if lib().orc_boot_picks(int(seed), int(R), int(h), int(n), _ptr(out)) != 0:
+        raise ValueError("invalid bootstrap size")
+    return out
 
 
 class Sim:

@@ -71,7 +71,7 @@ static void draw(const uint32_t key[2], uint64_t T, uint32_t slot, uint32_t tag,
     orc_philox4x32_10(ctr, key, x);
 }
 
-enum { TAG_FLIP = 0, TAG_EXCHANGE = 1, TAG_INIT = 2, TAG_PARTNER = 3 };
+enum { TAG_FLIP = 0, TAG_EXCHANGE = 1, TAG_INIT = 2, TAG_PARTNER = 3, TAG_BOOT = 4 };
 
 /* ------------------------------------------------------------------------ */
 /* Acceptance (Sec. II.A: states are sampled with weight 1/g(E)):           */
@@ -664,4 +664,29 @@ int orc_concat(const orc_config* c, const uint8_t* mask, const double* pieces, d
     }
     free(lo); free(hi); free(shift);
     return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Bootstrap over n independent runs (Sec. II.B, error analysis): each       */
+/* resample takes, for every window on its own, n of the runs' pieces with   */
+/* repetition.  The draws are Philox words like every other random number   */
+/* of the method (counter = resample, draw, window, stream tag).             */
+/* ------------------------------------------------------------------------ */
+int orc_boot_picks(uint64_t seed, int32_t R, int32_t h, int32_t n, int32_t* picks)
+{
+    if (n < 1 || h < 1 || R < 0) return -1;
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    for (int32_t r = 0; r <= R; ++r)
+        for (int32_t a = 0; a < h; ++a)
+            for (int32_t j = 0; j < n; ++j) {
+                int32_t* p = picks + ((size_t)r * h + a) * n + j;
+                if (r == 0) {
+                    *p = j;
+                    continue;
+                }
+                uint32_t ctr[4] = {(uint32_t)r, (uint32_t)j, (uint32_t)a, TAG_BOOT}, x[4];
+                orc_philox4x32_10(ctr, key, x);
+                *p = (int32_t)(((uint64_t)x[0] * (uint64_t)n) >> 32);
+            }
+    return 0;
 }

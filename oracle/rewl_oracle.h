@@ -95,6 +95,14 @@ int      orc_init_attempts_max(const orc_sim* s);         /* longest init drive 
 int      orc_concat(const orc_config* c, const uint8_t* mask, const double* pieces,
                     double* out, int32_t* join);
 
+/* --- n independent runs (Sec. II.B error analysis) ----------------------- */
+/* Which run's piece each draw of a resample takes: picks[(r*h + a)*n + j] for
+ * r = 0..R, window a < h, draw j < n.  Resample 0 is the ensemble itself (draw j
+ * takes run j); resample r >= 1 draws with repetition: run floor(x0 * n / 2^32)
+ * with x0 the first word of Philox4x32-10 at counter (r, j, a, 4) under key
+ * (seed low word, seed high word).  Returns 0, or -1 for n < 1, h < 1, R < 0.  */
+int      orc_boot_picks(uint64_t seed, int32_t R, int32_t h, int32_t n, int32_t* picks);
+
 #ifdef __cplusplus
 }
 #endif

@@ -79,6 +79,9 @@ _sigs = {
     "rewl_run_exact": ([_vp, ctypes.c_int64], ctypes.c_int),
     "rewl_get_window_lng": ([_vp, ctypes.c_int32, ctypes.c_int32, _vp], ctypes.c_int),
     "rewl_concat": ([_vp, ctypes.c_int32, _vp, _vp], ctypes.c_int),
+    "rewl_ensemble": ([_vp, _vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, _vp, _vp], ctypes.c_int),
+    "rewl_thermo": ([ctypes.c_int32, ctypes.c_int32, _vp, ctypes.c_int32, _vp, ctypes.c_int32, _vp, _vp,
+                     _vp], ctypes.c_int),
     "rewl_get_state": ([_vp, ctypes.c_int32] + [_vp] * 9, ctypes.c_int),
     "rewl_get_stats": ([_vp, ctypes.c_int32, _P(rewl_stats), _vp, _vp], ctypes.c_int),
     "rewl_set_timing": ([_vp, ctypes.c_int32], ctypes.c_int),
@@ -222,6 +225,29 @@ def rewl_concat(h, instance: int, W: int, n_windows: int):
     return out, join[: max(n_windows - 1, 0)]
 
 
+def rewl_ensemble(h, runs, R: int, seed: int, W: int, n_windows: int):
+    r = np.ascontiguousarray(runs, np.int32)
+    out = np.empty((R + 1, W), np.float64)
+    join = np.zeros((R + 1, max(n_windows - 1, 1)), np.int32)
+    _check(_lib.rewl_ensemble(h, _p(r), int(r.size), int(R), int(seed), _p(out), _p(join)), "rewl_ensemble")
+    return out, join[:, : max(n_windows - 1, 0)]
+
+
+def rewl_thermo(model, L: int, lng, T):
+    """u, c, f per spin, shape (rows, len(T)), for ln g rows over the model's bins."""
+    m = {"ising": 0, "potts": 1}.get(model, model)
+    x = np.ascontiguousarray(np.atleast_2d(lng), np.float64)
+    t = np.ascontiguousarray(np.atleast_1d(T), np.float64)
+    S, nT = x.shape[0], t.size
+    W = L * L + 1 if m == 0 else 2 * L * L + 1
+    if m in (0, 1) and x.shape[1] != W:
+        raise ValueError(f"ln g rows have {x.shape[1]} bins, the model needs {W}")
+    u, c, f = (np.empty((S, nT), np.float64) for _ in range(3))
+    _check(_lib.rewl_thermo(int(m), int(L), _p(x), int(S), _p(t), int(nT), _p(u), _p(c), _p(f)),
+           "rewl_thermo")
+    return u, c, f
+
+
 def rewl_get_state(h, instance: int, cfg: rewl_config) -> dict:
     W, WB, _, _ = rewl_layout(cfg)
     S, N, nw = cfg.n_windows * cfg.walkers_per_window, cfg.L * cfg.L, cfg.n_windows
@@ -335,6 +361,11 @@ class Rewl:
     def concat(self, i: int = 0):
         W = self.layouts[i][0]
         return rewl_concat(self.h, i, W, self.cfgs[i].n_windows)
+
+    def ensemble(self, runs, R: int = 0, seed: int = 1):
+        """Mean global ln g of the listed instances (row 0) and R bootstrap resamples."""
+        i = int(runs[0])
+        return rewl_ensemble(self.h, runs, R, seed, self.layouts[i][0], self.cfgs[i].n_windows)
 
     def set_initial_lng(self, lng, i: int = 0) -> None:
         rewl_set_initial_lng(self.h, i, lng)

@@ -9,7 +9,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "librewl.so")
 SOURCES = ["csrc/rewl_api.hip", "csrc/mlp.hip"]
-DEPS = ["csrc/rewl_api.hip", "csrc/rewl_kernels.hip", "csrc/rewl_device.hpp", "csrc/mlp.hip"]
+DEPS = ["csrc/rewl_api.hip", "csrc/rewl_kernels.hip", "csrc/rewl_device.hpp", "csrc/mlp.hip",
+        "csrc/ensemble_kernels.hip"]
 HEADERS = ["rewl.h", "rewl_mlp.h"]
 
 HIPCC_FLAGS = [

@@ -11,6 +11,7 @@
 
 #include "../../include/rewl.h"
 #include "rewl_kernels.hip"
+#include "ensemble_kernels.hip"
 
 using namespace rewl;
 
@@ -298,6 +299,17 @@ std::vector<Span> spans_of(rewl_handle* H, int i)
 }
 }  // namespace
 
+namespace {
+// device buffer released on every return path
+struct DevBuf {
+    void* p = nullptr;
+    hipError_t alloc(size_t bytes) { return hipMalloc(&p, bytes < 8 ? 8 : bytes); }
+    ~DevBuf() { if (p) (void)hipFree(p); }
+    template <class T> T* as() const { return (T*)p; }
+};
+constexpr size_t kEnsembleMaxBytes = size_t(16) << 30;
+}  // namespace
+
 extern "C" {
 
 const char* rewl_last_error(void) { return g_err.c_str(); }
@@ -463,7 +475,8 @@ static rewl_status create_impl(const rewl_config* cfgs, int32_t n, void* hip_str
         // 1024 walkers 1.39 vs 2.66 ms, Potts q=10 L=32 4096 walkers 1.78 vs
         // 3.50 ms per 10^4 attempts); with tens of thousands of walkers the lane
         // variant's width wins (the 64-instance batch).
-        const bool wave_ok = c.model == 0 ? c.L <= 64 : hi.N <= kWaveMaxSites;
+        // any lattice, as long as one walker's wave tables fit (the site map is bounded)
+        const bool wave_ok = wave_lds_bytes(c.model, c.L, hi.WB, 1) <= (size_t)lds_limit;
         int64_t total_walkers = 0;
         for (int u = 0; u < n; ++u) total_walkers += (int64_t)cfgs[u].n_windows * cfgs[u].walkers_per_window;
         hi.kind = REWL_SWEEP_LANE;
@@ -616,9 +629,7 @@ static rewl_status autotune(const rewl_config* cfgs, int32_t n, void* hip_stream
                             const rewl_tune& base, rewl_tune* best)
 {
     std::vector<rewl_tune> cand;
-    bool all_wave = true;
-    for (int i = 0; i < n; ++i)
-        all_wave = all_wave && (cfgs[i].model == 0 ? cfgs[i].L <= 64 : cfgs[i].L * cfgs[i].L <= kWaveMaxSites);
+    const bool all_wave = true;         // the wave variant runs every supported lattice
     for (int kb : {40, 53, 80, 0}) {
         rewl_tune t = base;
         t.sweep_kind = REWL_SWEEP_LANE;
@@ -884,6 +895,101 @@ rewl_status rewl_concat(rewl_handle* H, int32_t i, double* out_lng, int32_t* joi
     return REWL_OK;
 }
 
+rewl_status rewl_ensemble(rewl_handle* H, const int32_t* runs, int32_t n, int32_t R, uint64_t seed,
+                          double* out_lng, int32_t* join)
+{
+    if (!H || !runs || !out_lng) return fail(REWL_E_INVALID, "null argument");
+    if (n < 1 || n > 4096) return fail(REWL_E_INVALID, "n must be 1..4096");
+    if (R < 0 || R > 65534) return fail(REWL_E_INVALID, "R must be 0..65534");
+    for (int j = 0; j < n; ++j) {
+        rewl_status s = check_inst(H, runs[j]);
+        if (s != REWL_OK) return s;
+    }
+    const HostInst& h0 = H->inst[runs[0]];
+    for (int j = 1; j < n; ++j) {
+        const HostInst& hj = H->inst[runs[j]];
+        if (hj.cfg.model != h0.cfg.model || hj.cfg.L != h0.cfg.L || hj.dev.q != h0.dev.q ||
+            hj.lo != h0.lo || hj.hi != h0.hi || hj.WB != h0.WB)
+            return fail(REWL_E_INVALID, "runs " + std::to_string(runs[0]) + " and " +
+                                            std::to_string(runs[j]) + " differ in model, lattice or windows");
+    }
+    const int h = h0.h, WB = h0.WB, W = h0.W, nj = std::max(h - 1, 1);
+    const size_t rows = (size_t)R + 1;
+    const size_t mean_b = rows * h * WB * 8, out_b = rows * W * 8;
+    if (mean_b + out_b + rows * (nj * 4 + h * 8 + 4) > kEnsembleMaxBytes)
+        return fail(REWL_E_INVALID, "ensemble tables exceed 16 GiB: use fewer resamples per call");
+    std::vector<const double*> ptrs(n);
+    for (int j = 0; j < n; ++j) ptrs[j] = H->inst[runs[j]].dev.base;
+    DevBuf d_ptrs, d_mean, d_out, d_join, d_shift, d_status;
+    HIP_TRY(d_ptrs.alloc(n * sizeof(double*)));
+    HIP_TRY(d_mean.alloc(mean_b));
+    HIP_TRY(d_out.alloc(out_b));
+    HIP_TRY(d_join.alloc(rows * nj * 4));
+    HIP_TRY(d_shift.alloc(rows * h * 8));
+    HIP_TRY(d_status.alloc(rows * 4));
+    HIP_TRY(hipMemcpyAsync(d_ptrs.p, ptrs.data(), n * sizeof(double*), hipMemcpyHostToDevice, H->stream));
+    hipLaunchKernelGGL(k_boot_mean, dim3(h, (unsigned)rows), dim3(256), n * sizeof(int), H->stream,
+                       d_ptrs.as<const double*>(), n, h, WB, (uint32_t)seed, (uint32_t)(seed >> 32),
+                       d_mean.as<double>());
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_concat, dim3((unsigned)rows), dim3(256), 0, H->stream, H->d_insts, runs[0],
+                       d_mean.as<double>(), d_out.as<double>(), d_join.as<int32_t>(),
+                       d_shift.as<double>(), d_status.as<int32_t>());
+    HIP_TRY(hipGetLastError());
+    std::vector<int32_t> status(rows), jall;
+    HIP_TRY(hipMemcpyAsync(out_lng, d_out.p, out_b, hipMemcpyDeviceToHost, H->stream));
+    if (join && h > 1) {
+        jall.resize(rows * nj);
+        HIP_TRY(hipMemcpyAsync(jall.data(), d_join.p, rows * nj * 4, hipMemcpyDeviceToHost, H->stream));
+    }
+    HIP_TRY(hipMemcpyAsync(status.data(), d_status.p, rows * 4, hipMemcpyDeviceToHost, H->stream));
+    HIP_TRY(hipStreamSynchronize(H->stream));
+    if (join && h > 1) std::memcpy(join, jall.data(), rows * nj * 4);
+    for (size_t r = 0; r < rows; ++r)
+        if (status[r] != 0)
+            return fail(REWL_E_STATE, "row " + std::to_string(r) + ": no valid join point in some overlap");
+    return REWL_OK;
+}
+
+rewl_status rewl_thermo(int32_t model, int32_t L, const double* lng, int32_t S, const double* T,
+                        int32_t nT, double* u, double* c, double* f)
+{
+    if (!lng || !T) return fail(REWL_E_INVALID, "null argument");
+    if (model != 0 && model != 1) return fail(REWL_E_INVALID, "model must be 0 (Ising) or 1 (Potts)");
+    if (L < 2 || L > 4096) return fail(REWL_E_INVALID, "L must be 2..4096");
+    if (S < 1 || S > 65535 || nT < 1) return fail(REWL_E_INVALID, "need 1 <= S <= 65535 rows and nT >= 1");
+    const int N = L * L, W = model == 0 ? N + 1 : 2 * N + 1;
+    for (int t = 0; t < nT; ++t)
+        if (!(T[t] > 0.0) || !std::isfinite(T[t])) return fail(REWL_E_INVALID, "temperatures must be finite and > 0");
+    for (int s = 0; s < S; ++s) {
+        bool any = false;
+        for (int b = 0; b < W; ++b) {
+            const double v = lng[(size_t)s * W + b];
+            if (std::isnan(v) || v == HUGE_VAL)
+                return fail(REWL_E_INVALID, "row " + std::to_string(s) + ": ln g holds NaN or +inf");
+            any |= v != -HUGE_VAL;
+        }
+        if (!any) return fail(REWL_E_INVALID, "row " + std::to_string(s) + ": no energy level occurs");
+    }
+    const size_t in_b = (size_t)S * W * 8, out_b = (size_t)S * nT * 8;
+    DevBuf d_lng, d_T, d_u, d_c, d_f;
+    HIP_TRY(d_lng.alloc(in_b));
+    HIP_TRY(d_T.alloc((size_t)nT * 8));
+    if (u) HIP_TRY(d_u.alloc(out_b));
+    if (c) HIP_TRY(d_c.alloc(out_b));
+    if (f) HIP_TRY(d_f.alloc(out_b));
+    HIP_TRY(hipMemcpy(d_lng.p, lng, in_b, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(d_T.p, T, (size_t)nT * 8, hipMemcpyHostToDevice));
+    hipLaunchKernelGGL(k_thermo, dim3((nT + kThermoT - 1) / kThermoT, S), dim3(64), 0, 0,
+                       d_lng.as<double>(), W, model, N, d_T.as<double>(), nT, d_u.as<double>(),
+                       d_c.as<double>(), d_f.as<double>());
+    HIP_TRY(hipGetLastError());
+    if (u) HIP_TRY(hipMemcpy(u, d_u.p, out_b, hipMemcpyDeviceToHost));
+    if (c) HIP_TRY(hipMemcpy(c, d_c.p, out_b, hipMemcpyDeviceToHost));
+    if (f) HIP_TRY(hipMemcpy(f, d_f.p, out_b, hipMemcpyDeviceToHost));
+    HIP_TRY(hipDeviceSynchronize());
+    return REWL_OK;
+}
 
 rewl_status rewl_checkpoint(rewl_handle* H, void* buf, size_t* len)
 {

@@ -98,7 +98,7 @@ template <int MODEL, int WPR>
 __device__ void sweep_tile(const Inst& I, const Tile& tile, char* smem)
 {
     const int a = tile.window, nw = tile.nw, lane = threadIdx.x;
-    const int WB = I.WB, L = I.L, S = I.S, N = I.N;
+    const int WB = I.WB, L = I.L, N = I.N;
     const int slot0 = a * I.m + tile.r0;
     const int lo = I.lo[a];
     const int nbins = WB + 2 * kPad;
@@ -328,19 +328,21 @@ __global__ void __launch_bounds__(64) k_sweep(const Inst* __restrict__ insts,
 // LDS: base [nbins] shared by the block's walkers (all of one window), then per
 // wave its counts H [nbins], then (Potts) per wave its lattice [N].
 // LDS of the wave variant: the window's base table (shared), then per wave its
-// histogram, its site map (one 64-bit attempt mask per site) and its lattice
-// (Potts bytes, Ising one 64-bit word per row).
+// histogram, its site map and its lattice (Potts bytes, Ising 64-bit words, wpr
+// per row).  The site map has one 64-bit attempt mask per entry, min(N, 4096)
+// entries; larger lattices share entries between sites (site mod 4096), which
+// only adds attempts to the out-of-date sets, never removes one.
+constexpr int kWaveMapMax = 4096;
+__host__ __device__ inline int wave_map_entries(int N) { return N < kWaveMapMax ? N : kWaveMapMax; }
 __host__ __device__ inline size_t wave_lds_bytes(int model, int L, int WB, int G)
 {
     const size_t nb = (size_t)WB + 2 * kPad, N = (size_t)L * L;
     size_t s = nb * 8 + (size_t)G * nb * 4;
     s = (s + 7) & ~size_t(7);
-    s += (size_t)G * N * 8;
-    s += model == 1 ? (size_t)G * N : (size_t)G * L * 8;
+    s += (size_t)G * wave_map_entries((int)N) * 8;
+    s += model == 1 ? (size_t)G * N : (size_t)G * L * ((L + 63) / 64) * 8;
     return s;
 }
-// the site map bounds the wave variant to lattices of at most 4096 sites
-constexpr int kWaveMaxSites = 4096;
 
 __device__ __forceinline__ uint32_t rl(uint32_t v, int l)
 {
@@ -366,6 +368,20 @@ __device__ __forceinline__ int ising_d(uint64_t w, uint64_t wu, uint64_t wd, int
     const uint32_t sp = (uint32_t)(w >> c) & 1u;
     const uint32_t ones = ((uint32_t)(wu >> c) & 1u) + ((uint32_t)(wd >> c) & 1u) +
                           ((uint32_t)(w >> cl) & 1u) + ((uint32_t)(w >> cr) & 1u);
+    return (sp ? (int)ones : 4 - (int)ones) - 2;
+}
+
+// Bin change of flipping Ising spin (r, c) on rows of wpr 64-bit words.
+__device__ __forceinline__ int ising_d_words(const uint64_t* rows, int wpr, int r, int ru, int rd, int c,
+                                             int L)
+{
+    if (wpr == 1) return ising_d(rows[r], rows[ru], rows[rd], c, L);
+    auto spin = [&](int rr, int cc) -> uint32_t {
+        return (uint32_t)(rows[rr * wpr + (cc >> 6)] >> (cc & 63)) & 1u;
+    };
+    const int cl = c == 0 ? L - 1 : c - 1, cr = c == L - 1 ? 0 : c + 1;
+    const uint32_t sp = spin(r, c);
+    const uint32_t ones = spin(ru, c) + spin(rd, c) + spin(r, cl) + spin(r, cr);
     return (sp ? (int)ones : 4 - (int)ones) - 2;
 }
 
@@ -401,10 +417,14 @@ __device__ void sweep_wave(const Inst& I, const Tile& tile, char* smem)
     const bool active = wave < G;
     const int r = tile.r0 + wave, slot = a * I.m + r;
     uint32_t* lH = (uint32_t*)(lbase + nbins) + (size_t)wave * nbins;
+    const int M = wave_map_entries(N), mmask = M == kWaveMapMax ? kWaveMapMax - 1 : -1;
+    const int wpr = I.wpr;                                    // Ising words per row
     const size_t off_map = ((size_t)nbins * 8 + (size_t)G * nbins * 4 + 7) & ~size_t(7);
-    uint64_t* lmap = (uint64_t*)(smem + off_map) + (size_t)wave * N;
-    uint8_t* llat = (uint8_t*)(smem + off_map + (size_t)G * N * 8) + (size_t)wave * N;
-    uint64_t* lrow = (uint64_t*)(smem + off_map + (size_t)G * N * 8) + (size_t)wave * L;
+    uint64_t* lmap = (uint64_t*)(smem + off_map) + (size_t)wave * M;
+    uint8_t* llat = (uint8_t*)(smem + off_map + (size_t)G * M * 8) + (size_t)wave * N;
+    uint64_t* lrow = (uint64_t*)(smem + off_map + (size_t)G * M * 8) + (size_t)wave * L * wpr;
+    // site -> map entry: the site itself when every site has one, else site mod 4096
+    auto ent = [&](int site) { return mmask < 0 ? site : (site & mmask); };
     if (active) {
         for (int i = lane; i < nbins; i += 64) {
             const int b = i - kPad;
@@ -413,9 +433,9 @@ __device__ void sweep_wave(const Inst& I, const Tile& tile, char* smem)
                 hv = (b < width && I.mask[lo + b]) ? I.H[(size_t)slot * WB + b] : 0xffffffffu;
             lH[i] = hv;
         }
-        for (int i = lane; i < N; i += 64) lmap[i] = 0;
+        for (int i = lane; i < M; i += 64) lmap[i] = 0;
         if (MODEL == 0) {
-            if (lane < L) lrow[lane] = I.lat[(size_t)slot * L + lane];
+            for (int i = lane; i < L * wpr; i += 64) lrow[i] = I.lat[(size_t)slot * L * wpr + i];
         } else {
             for (int i = lane; i < N; i += 64) llat[i] = I.plat[(size_t)slot * N + i];
         }
@@ -469,7 +489,7 @@ __device__ void sweep_wave(const Inst& I, const Tile& tile, char* smem)
         uint32_t nv = 0;                  // Potts: proposed state
         auto evaluate = [&]() {           // on the lattice as it stands
             if (MODEL == 0) {
-                d = ising_d(lrow[rr], lrow[ru], lrow[rd], cc, L);
+                d = ising_d_words(lrow, wpr, rr, ru, rd, cc, L);
             } else {
                 const uint32_t s0 = llat[site];
                 const uint32_t n0 = llat[s_up], n1 = llat[s_dn], n2 = llat[s_lf], n3 = llat[s_rt];
@@ -484,10 +504,11 @@ __device__ void sweep_wave(const Inst& I, const Tile& tile, char* smem)
         const double vbl = threshold_of(u53_of(x));
         const double vbl2 = vbl - 2.0 * kBand;    // below it a reject is certain
         // earlier attempts of the chunk whose site lies in this attempt's neighbourhood
-        if (lane < n) atomicOr((unsigned long long*)&lmap[site], 1ull << lane);
-        const uint64_t pm = (lmap[site] | lmap[s_up] | lmap[s_dn] | lmap[s_lf] | lmap[s_rt]) &
+        if (lane < n) atomicOr((unsigned long long*)&lmap[ent(site)], 1ull << lane);
+        const uint64_t pm = (lmap[ent(site)] | lmap[ent(s_up)] | lmap[ent(s_dn)] | lmap[ent(s_lf)] |
+                             lmap[ent(s_rt)]) &
                             ((1ull << lane) - 1);
-        if (lane < n) lmap[site] = 0;
+        if (lane < n) lmap[ent(site)] = 0;
         const uint64_t live = n == 64 ? ~0ull : ((1ull << n) - 1);
         uint64_t F = 0;                   // attempts flipped since the lanes last evaluated
         // B = lngc - i incv: with it, lane j's ln g difference is B - gp + j incv
@@ -532,7 +553,8 @@ __device__ void sweep_wave(const Inst& I, const Tile& tile, char* smem)
             const uint64_t flips = (zero & below) | (move ? (1ull << js) : 0ull);
             if (flips) {
                 if ((flips >> lane) & 1u) {
-                    if (MODEL == 0) atomicXor((unsigned long long*)&lrow[rr], 1ull << cc);
+                    if (MODEL == 0)
+                        atomicXor((unsigned long long*)&lrow[rr * wpr + (cc >> 6)], 1ull << (cc & 63));
                     else llat[site] = (uint8_t)nv;
                 }
                 F |= flips;
@@ -569,7 +591,7 @@ __device__ void sweep_wave(const Inst& I, const Tile& tile, char* smem)
         I.H[(size_t)slot * WB + i] = hv == 0xffffffffu ? 0u : hv;
     }
     if (MODEL == 0) {
-        if (lane < L) I.lat[(size_t)slot * L + lane] = lrow[lane];
+        for (int i = lane; i < L * wpr; i += 64) I.lat[(size_t)slot * L * wpr + i] = lrow[i];
     } else {
         for (int i = lane; i < N; i += 64) I.plat[(size_t)slot * N + i] = llat[i];
     }
@@ -881,7 +903,9 @@ __global__ void k_init(const Inst* __restrict__ insts, const int32_t* __restrict
 // ------------------------------------------------------------ concatenate
 // Sec. II.B: per overlap, 5-point derivative of both pieces with step d,
 // join where they agree best (ties to the lower bin, joins ascending), shift
-// the pieces, cut the tails, normalise to sum g = q^N.  One block per call.
+// the pieces, cut the tails, normalise to sum g = q^N.  One block per set of
+// pieces: block r joins pieces[r][h][WB] into out[r][W] (join[r][max(h-1,1)],
+// shift[r][h], status[r]); all sets share the windows of instance `inst`.
 __global__ void __launch_bounds__(256) k_concat(const Inst* __restrict__ insts, int inst,
                                                 const double* __restrict__ pieces,
                                                 double* __restrict__ out,
@@ -892,6 +916,12 @@ __global__ void __launch_bounds__(256) k_concat(const Inst* __restrict__ insts, 
     __shared__ int rb[256];
     const Inst& I = insts[inst];
     const int h = I.h, WB = I.WB, W = I.W, tid = threadIdx.x;
+    const size_t set = blockIdx.x;
+    pieces += set * h * WB;
+    out += set * W;
+    join += set * (h > 1 ? h - 1 : 1);
+    shift += set * h;
+    status += set;
     if (tid == 0) {
         shift[0] = 0.0;
         *status = 0;

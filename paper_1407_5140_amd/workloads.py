@@ -13,7 +13,8 @@ _BATCH_TYPES = [("ising", 2, 16), ("ising", 2, 24), ("ising", 2, 32), ("ising", 
 
 def single(name: str) -> dict:
     """The single-instance workloads: Ising L=8 (4 windows, 1 walker each, ln f to 2^-20),
-    Ising L=32 (8 windows x 16 walkers, ln f to 2^-20),
+    Ising L=32 (8 windows x 16 walkers, ln f to 2^-20), 10-state Potts L=100 (the paper's
+    77 windows of 1001 bins, 8 walkers each),
     Ising L=64 (16 windows x 64 walkers) and 10-state Potts L=32 (32 windows x 128
     walkers), both to ln f = 2^-27; 75% overlap, flatness 4/5, X = 10^4, seed 1."""
     table = {
@@ -21,6 +22,8 @@ def single(name: str) -> dict:
         "ising32": dict(model="ising", q=2, L=32, n_windows=8, m=16, kfinal=20, X=10000, seed=1),
         "ising64": dict(model="ising", q=2, L=64, n_windows=16, m=64, kfinal=27, X=10000, seed=1),
         "potts32": dict(model="potts", q=10, L=32, n_windows=32, m=128, kfinal=27, X=10000, seed=1),
+        # the paper's smallest Potts lattice (Sec. IV.A): 77 windows of 1001 bins, 75 % overlap
+        "potts100": dict(model="potts", q=10, L=100, n_windows=77, m=8, kfinal=27, X=10000, seed=1),
     }
     return dict(table[name])
 
