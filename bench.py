@@ -384,8 +384,44 @@ def ensemble_study(rw, args) -> dict:
            "T_peak": float(peak[0]), "T_peak_err": float(np.std(peak[1:])) if R > 1 else None,
            "c_max": float(cmax[0]), "c_max_err": float(np.std(cmax[1:])) if R > 1 else None,
            "joins_spread": float(np.mean(np.std(joins[1:], axis=0))) if R > 1 else None}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = ensemble_cpu_baseline(kws, n, R, T, args.cpu_budget)
     log(json.dumps(out))
     return out
+
+
+def ensemble_cpu_baseline(kws, n, R, T, budget_s) -> dict:
+    """The oracle on the host beside the device: its REWL run on one of the n runs
+    (bounded intervals), and its mean + bootstrap and canonical averages on
+    synthetic tables of the same shape, timed on a few rows and scaled to R + 1."""
+    import oracle as O
+    from oracle import ensemble as EN
+    res = {"sweep": cpu_baseline([kws[0]], budget_s)}
+    c = O.make_config(**kws[0])
+    W = O.n_bins(c)
+    lo, hi = O.layout(c)
+    WB = int((hi - lo).max()) + 1
+    rng = np.random.default_rng(0)
+    b = np.arange(W)
+    tab = 3000.0 * np.sin(np.pi * b / (W - 1))
+    runs = np.zeros((n, len(lo), WB))
+    for j in range(n):
+        t = tab + rng.normal(0, 0.02, W) + 17.0 * j
+        for a in range(len(lo)):
+            runs[j, a, : hi[a] - lo[a] + 1] = t[lo[a]: hi[a] + 1]
+    mask = O.mask_rule(c)
+    r_s = 8
+    t0 = time.perf_counter()
+    rows, _ = EN.ensemble(c, mask, runs, R=r_s - 1, seed=1)
+    t_ens = (time.perf_counter() - t0) * (R + 1) / r_s
+    t0 = time.perf_counter()
+    EN.canonical("potts", kws[0]["L"], rows[0], T)
+    t_th = (time.perf_counter() - t0) * (R + 1)
+    res["ensemble_seconds"] = t_ens
+    res["thermo_seconds"] = t_th
+    res["sample"] = (f"ensemble: {r_s} rows timed, scaled to {R + 1}; canonical averages: one row of "
+                     f"{T.size} temperatures timed, scaled to {R + 1} rows; one thread (numpy/C)")
+    return res
 
 
 def main(argv=None):

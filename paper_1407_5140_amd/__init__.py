@@ -22,6 +22,7 @@ if not os.path.exists(LIB_PATH):
 _lib = ctypes.CDLL(LIB_PATH)
 
 REWL_OK = 0
+REWL_E_INVALID = -1
 _STATUS = {0: "OK", -1: "INVALID", -2: "EMPTY_WINDOW", -3: "NOMEM", -4: "DEVICE", -5: "OVERFLOW",
            -6: "INIT_STUCK", -7: "STATE"}
 

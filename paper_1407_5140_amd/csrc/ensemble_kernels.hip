@@ -11,31 +11,31 @@ namespace rewl {
 
 enum : uint32_t { kTagBoot = 4 };
 
-// Grid (h, R + 1), 256 threads, n ints of dynamic LDS.  runs[i] points at run
-// i's window tables [h][WB]; mean receives [R + 1][h][WB].  Resample 0 takes
-// run j for draw j; resample r >= 1 takes run floor(x0 n / 2^32) for draw j
-// of window a, x0 the first Philox word at counter (r, j, a, kTagBoot).  The
-// sum runs in draw order and is then divided by n.
+// Grid (h, R + 1), 256 threads, n pointers of dynamic LDS.  runs[i] points at
+// run i's window tables [h][WB]; mean receives [R + 1][h][WB].  Resample 0
+// takes run j for draw j; resample r >= 1 takes run floor(x0 n / 2^32) for
+// draw j of window a, x0 the first Philox word at counter (r, j, a, kTagBoot).
+// The sum runs in draw order and is then divided by n.
 __global__ void __launch_bounds__(256) k_boot_mean(const double* const* __restrict__ runs, int n,
                                                    int h, int WB, uint32_t k0, uint32_t k1,
                                                    double* __restrict__ mean)
 {
-    extern __shared__ int pick[];
+    extern __shared__ const double* piece[];   // draw j -> the picked run's table of window a
     const int a = blockIdx.x, r = blockIdx.y;
+    const size_t off = (size_t)a * WB;
     for (int j = threadIdx.x; j < n; j += blockDim.x) {
         int p = j;
         if (r > 0) {
             const u32x4 x = philox10((uint32_t)r, (uint32_t)j, (uint32_t)a, kTagBoot, k0, k1);
             p = (int)(((uint64_t)x.x * (uint64_t)n) >> 32);
         }
-        pick[j] = p;
+        piece[j] = runs[p] + off;
     }
     __syncthreads();
     double* o = mean + ((size_t)r * h + a) * WB;
-    const size_t off = (size_t)a * WB;
     for (int b = threadIdx.x; b < WB; b += blockDim.x) {
         double acc = 0.0;
-        for (int j = 0; j < n; ++j) acc += runs[pick[j]][off + b];
+        for (int j = 0; j < n; ++j) acc += piece[j][b];
         o[b] = acc / (double)n;
     }
 }

@@ -928,7 +928,7 @@ rewl_status rewl_ensemble(rewl_handle* H, const int32_t* runs, int32_t n, int32_
     HIP_TRY(d_shift.alloc(rows * h * 8));
     HIP_TRY(d_status.alloc(rows * 4));
     HIP_TRY(hipMemcpyAsync(d_ptrs.p, ptrs.data(), n * sizeof(double*), hipMemcpyHostToDevice, H->stream));
-    hipLaunchKernelGGL(k_boot_mean, dim3(h, (unsigned)rows), dim3(256), n * sizeof(int), H->stream,
+    hipLaunchKernelGGL(k_boot_mean, dim3(h, (unsigned)rows), dim3(256), n * sizeof(double*), H->stream,
                        d_ptrs.as<const double*>(), n, h, WB, (uint32_t)seed, (uint32_t)(seed >> 32),
                        d_mean.as<double>());
     HIP_TRY(hipGetLastError());
@@ -987,7 +987,7 @@ rewl_status rewl_thermo(int32_t model, int32_t L, const double* lng, int32_t S, 
     if (u) HIP_TRY(hipMemcpy(u, d_u.p, out_b, hipMemcpyDeviceToHost));
     if (c) HIP_TRY(hipMemcpy(c, d_c.p, out_b, hipMemcpyDeviceToHost));
     if (f) HIP_TRY(hipMemcpy(f, d_f.p, out_b, hipMemcpyDeviceToHost));
-    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipStreamSynchronize(nullptr));
     return REWL_OK;
 }
 

@@ -111,3 +111,20 @@ def test_balanced_layout_equalises_difficulty(rw, model, q, L, h):
     sums = np.array([rho[l:u + 1].sum() for l, u in zip(lo, hi)])
     assert sums.max() / sums.min() < 1.25
     assert ((hi[:-1] - lo[1:] + 1) >= 8).all()
+
+
+def test_thermo_and_ensemble_validate_on_the_host(rw):
+    """Bad arguments are rejected before any device call (runs without a GPU)."""
+    lg = np.zeros(17)
+    inf_row = lg.copy()
+    inf_row[2] = np.inf
+    cases = [("ising", 4, lg, [0.0]), ("ising", 4, lg, [np.nan]), ("ising", 4, lg, [-1.0]),
+             (5, 4, lg, [1.0]), ("ising", 4, np.full(17, -np.inf), [1.0]), ("ising", 1, np.zeros(2), [1.0]),
+             ("ising", 4, inf_row, [1.0])]
+    for args in cases:
+        with pytest.raises(rw.RewlError) as e:
+            rw.rewl_thermo(*args)
+        assert e.value.status == rw.REWL_E_INVALID
+    with pytest.raises(rw.RewlError) as e:
+        rw.rewl_ensemble(None, [0], 1, 1, 17, 4)
+    assert e.value.status == rw.REWL_E_INVALID
