@@ -94,7 +94,7 @@ def test_device_acceptance_predicate_exact(rw):
 
 # ----------------------------------------------------------- lockstep runs
 SMALL = [
-    dict(model="ising", L=8, n_windows=4, m=1, kfinal=20, X=10000, seed=1),       # config-1 geometry
+    dict(model="ising", L=8, n_windows=4, m=1, kfinal=20, X=10000, seed=1),       # the Ising L=8 workload
     dict(model="ising", L=16, n_windows=4, m=8, kfinal=12, X=3000, seed=5),
     dict(model="potts", q=10, L=8, n_windows=4, m=4, kfinal=12, X=3000, seed=7),
     dict(model="potts", q=4, L=12, n_windows=6, m=16, overlap=(1, 2), kfinal=12, X=2000, seed=11),
@@ -128,7 +128,7 @@ def test_lockstep_small(rw, kw, kind):
     assert gpu.info()["sweep_kind"] == kind          # every lattice here fits either variant
 
 
-def test_config1_full_run_bitwise(rw):
+def test_ising_L8_full_run_bitwise(rw):
     """Ising L=8, 4 windows, m=1, ln f 1 -> 2^-20, X=1e4, seed 1: run to convergence."""
     kw = dict(model="ising", L=8, n_windows=4, m=1, kfinal=20, X=10000, seed=1)
     gpu, orc, done = _lockstep(rw, kw, 100000, every=25)
@@ -145,11 +145,11 @@ def test_config1_full_run_bitwise(rw):
 
 
 @pytest.mark.parametrize("kw", [
-    dict(model="ising", L=64, n_windows=16, m=64, kfinal=27, X=10000, seed=1),      # config 2
-    dict(model="potts", q=10, L=32, n_windows=32, m=128, kfinal=27, X=10000, seed=1),  # config 3
-], ids=["config2-ising64", "config3-potts32"])
+    dict(model="ising", L=64, n_windows=16, m=64, kfinal=27, X=10000, seed=1),
+    dict(model="potts", q=10, L=32, n_windows=32, m=128, kfinal=27, X=10000, seed=1),
+], ids=["ising-L64-h16-m64", "potts-q10-L32-h32-m128"])
 @pytest.mark.parametrize("kind", ["auto", "lane"])
-def test_full_size_configs_first_intervals(rw, kw, kind):
+def test_full_size_workloads_first_intervals(rw, kw, kind):
     _lockstep(rw, kw, 2, tune=_tune(rw, kind))
 
 

@@ -343,7 +343,7 @@ def _concat_error(sim, exact):
 
 
 def test_rewl_converges_to_exact_ising_L8(golden):
-    """Config-1 geometry (4 windows, o = 3/4) with m = 16 walkers, ln f -> 2^-20."""
+    """The Ising L=8 geometry (4 windows, o = 3/4) with m = 16 walkers, ln f -> 2^-20."""
     exact = X.ln_g(golden.counts("ising_q2_L8_counts.txt"))
     c = O.make_config("ising", L=8, n_windows=4, m=16, kfinal=20, seed=1)
     sim = O.Sim(c)
