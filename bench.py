@@ -363,6 +363,15 @@ def ensemble_study(rw, args) -> dict:
     sts = [g.stats(i) for i in range(n)]
     attempts = sum(s["attempts"] for s in sts)
     log(f"run {t_run:.1f} s, {attempts / t_run:.4g} attempts/s, converged {done}")
+    # windows that have not reached the final ln f, with their energy ranges per spin
+    _, _, wlo, whi = g.layouts[0]
+    N = base["L"] ** 2
+    behind = []
+    for i in range(n):
+        k = g.state(i)["k"]
+        behind.append([[int(a), int(k[a]), round((wlo[a] - 2 * N) / N, 4), round((whi[a] - 2 * N) / N, 4)]
+                       for a in range(len(k)) if k[a] < base["kfinal"]])
+    log(f"windows behind (window, k, E/N from, to): {behind}")
     R = args.ens_R
     t0 = time.perf_counter()
     rows, joins = g.ensemble(list(range(n)), R=R, seed=1)
@@ -379,6 +388,7 @@ def ensemble_study(rw, args) -> dict:
                        f"m={base['m']}, ln f -> 2^-{base['kfinal']}, {n} runs",
            "converged": bool(done), "run_seconds": t_run, "attempts_per_s": attempts / t_run,
            "min_k": [s["min_k"] for s in sts], "intervals": sts[0]["intervals"],
+           "windows_behind": behind,
            "resamples": R, "ensemble_seconds": t_ens, "thermo_seconds": t_th,
            "thermo_grid": [float(T[0]), float(T[-1]), int(T.size)],
            "T_peak": float(peak[0]), "T_peak_err": float(np.std(peak[1:])) if R > 1 else None,

@@ -208,7 +208,7 @@ rewl_status enqueue_interval(rewl_handle* H, bool time_it)
     if (time_it) HIP_TRY(hipEventRecord(H->ev[2], H->stream));
     hipLaunchKernelGGL(k_merge, dim3(H->nmerge), dim3(256), 0, H->stream, H->d_insts, H->d_merge);
     if (H->exch_threads > 0)
-        hipLaunchKernelGGL(k_exchange, dim3((H->exch_threads + 255) / 256), dim3(256), 0, H->stream,
+        hipLaunchKernelGGL(k_exchange, dim3((H->exch_threads + 3) / 4), dim3(256), 0, H->stream,
                            H->d_insts, H->d_exch_start, H->n);
     hipLaunchKernelGGL(k_advance, dim3((H->n + 63) / 64), dim3(64), 0, H->stream, H->d_insts, H->n);
     if (time_it) HIP_TRY(hipEventRecord(H->ev[3], H->stream));

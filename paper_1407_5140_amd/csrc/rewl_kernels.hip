@@ -399,7 +399,9 @@ __device__ __forceinline__ int ising_d_words(const uint64_t* rows, int wpr, int 
 //   those attempts were rejected or were accepted with d = 0 (a move within the
 //   bin, always accepted).  The run ends at the first accepted move with d != 0,
 //   or before the first attempt that a flip of the run made out of date.
-template <int MODEL>
+// WIDE: N > 4096 (site map entries shared mod 4096; Ising rows of several
+// words).  The narrow form keeps the one-word rows and the direct map.
+template <int MODEL, bool WIDE>
 __device__ void sweep_wave(const Inst& I, const Tile& tile, char* smem)
 {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -417,14 +419,14 @@ __device__ void sweep_wave(const Inst& I, const Tile& tile, char* smem)
     const bool active = wave < G;
     const int r = tile.r0 + wave, slot = a * I.m + r;
     uint32_t* lH = (uint32_t*)(lbase + nbins) + (size_t)wave * nbins;
-    const int M = wave_map_entries(N), mmask = M == kWaveMapMax ? kWaveMapMax - 1 : -1;
-    const int wpr = I.wpr;                                    // Ising words per row
+    const int M = WIDE ? kWaveMapMax : N;
+    const int wpr = WIDE ? I.wpr : 1;                         // Ising words per row
     const size_t off_map = ((size_t)nbins * 8 + (size_t)G * nbins * 4 + 7) & ~size_t(7);
     uint64_t* lmap = (uint64_t*)(smem + off_map) + (size_t)wave * M;
     uint8_t* llat = (uint8_t*)(smem + off_map + (size_t)G * M * 8) + (size_t)wave * N;
     uint64_t* lrow = (uint64_t*)(smem + off_map + (size_t)G * M * 8) + (size_t)wave * L * wpr;
     // site -> map entry: the site itself when every site has one, else site mod 4096
-    auto ent = [&](int site) { return mmask < 0 ? site : (site & mmask); };
+    auto ent = [&](int site) { return WIDE ? (site & (kWaveMapMax - 1)) : site; };
     if (active) {
         for (int i = lane; i < nbins; i += 64) {
             const int b = i - kPad;
@@ -554,7 +556,8 @@ __device__ void sweep_wave(const Inst& I, const Tile& tile, char* smem)
             if (flips) {
                 if ((flips >> lane) & 1u) {
                     if (MODEL == 0)
-                        atomicXor((unsigned long long*)&lrow[rr * wpr + (cc >> 6)], 1ull << (cc & 63));
+                        atomicXor((unsigned long long*)&lrow[WIDE ? rr * wpr + (cc >> 6) : rr],
+                                  1ull << (cc & 63));
                     else llat[site] = (uint8_t)nv;
                 }
                 F |= flips;
@@ -634,8 +637,14 @@ __global__ void __launch_bounds__(512) k_sweep_wave(const Inst* __restrict__ ins
     const Tile tile = tiles[blockIdx.x];
     const Inst& I = insts[tile.inst];
     if (I.ctr->all_done) return;
-    if (I.model == 0) sweep_wave<0>(I, tile, smem);
-    else sweep_wave<1>(I, tile, smem);
+    const bool wide = I.N > kWaveMapMax;
+    if (I.model == 0) {
+        if (wide) sweep_wave<0, true>(I, tile, smem);
+        else sweep_wave<0, false>(I, tile, smem);
+    } else {
+        if (wide) sweep_wave<1, true>(I, tile, smem);
+        else sweep_wave<1, false>(I, tile, smem);
+    }
 }
 
 // ------------------------------------------------------------------- merge
@@ -708,20 +717,23 @@ __global__ void __launch_bounds__(256) k_merge(const Inst* __restrict__ insts,
 // c drawn once per (t, a).  Eq. (1) in log form, decided exactly; on accept the
 // two configurations (lattice and energy) change places, ln g and H stay.
 __global__ void __launch_bounds__(256) k_exchange(const Inst* __restrict__ insts,
-                                                  const int32_t* __restrict__ thread_start,
+                                                  const int32_t* __restrict__ pair_start,
                                                   int n_inst)
 {
-    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= thread_start[n_inst]) return;
+    // one wave per proposing walker: every lane takes the same decision from the
+    // same values, then the lanes swap the two configurations together
+    const int lane = threadIdx.x & 63;
+    const int gw = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    if (gw >= pair_start[n_inst]) return;
     int lo_i = 0, hi_i = n_inst - 1;
     while (lo_i < hi_i) {
         int mid = (lo_i + hi_i + 1) >> 1;
-        if (thread_start[mid] <= gid) lo_i = mid;
+        if (pair_start[mid] <= gw) lo_i = mid;
         else hi_i = mid - 1;
     }
     const Inst& I = insts[lo_i];
     if (!I.exch || I.ctr->all_done) return;
-    const int local = gid - thread_start[lo_i];
+    const int local = gw - pair_start[lo_i];
     const int m = I.m, a = local / m, r = local - a * m;
     const int64_t t = I.ctr->t;
     if ((a & 1) != (int)(t & 1)) return;
@@ -750,37 +762,41 @@ __global__ void __launch_bounds__(256) k_exchange(const Inst* __restrict__ insts
             const int nwords = I.L * I.wpr;
             uint64_t* pi = I.lat + (size_t)i * nwords;
             uint64_t* pj = I.lat + (size_t)j * nwords;
-            for (int w = 0; w < nwords; ++w) {
+            for (int w = lane; w < nwords; w += 64) {
                 const uint64_t x = pi[w];
                 pi[w] = pj[w];
                 pj[w] = x;
             }
         } else {
-            uint32_t* pi = (uint32_t*)(I.plat + (size_t)i * I.N);   // N % 4 == 0 or byte tail
-            uint32_t* pj = (uint32_t*)(I.plat + (size_t)j * I.N);
-            if ((I.N & 3) == 0) {
-                for (int w = 0; w < (I.N >> 2); ++w) {
-                    const uint32_t x = pi[w];
+            uint8_t* pi = I.plat + (size_t)i * I.N;
+            uint8_t* pj = I.plat + (size_t)j * I.N;
+            if ((I.N & 15) == 0) {                  // rows of 16-byte words (slots are N apart)
+                uint4* qi = (uint4*)pi;
+                uint4* qj = (uint4*)pj;
+                for (int w = lane; w < (I.N >> 4); w += 64) {
+                    const uint4 x = qi[w];
+                    qi[w] = qj[w];
+                    qj[w] = x;
+                }
+            } else {
+                for (int w = lane; w < I.N; w += 64) {
+                    const uint8_t x = pi[w];
                     pi[w] = pj[w];
                     pj[w] = x;
                 }
-            } else {
-                uint8_t* bi8 = I.plat + (size_t)i * I.N;
-                uint8_t* bj8 = I.plat + (size_t)j * I.N;
-                for (int w = 0; w < I.N; ++w) {
-                    const uint8_t x = bi8[w];
-                    bi8[w] = bj8[w];
-                    bj8[w] = x;
-                }
             }
         }
-        I.bin[i] = bj;
-        I.bin[j] = bi;
-        atomicAdd((unsigned long long*)&I.ex_acc[a], 1ull);
     }
-    atomicAdd((unsigned long long*)&I.ex_prop[a], 1ull);
-    I.swaps[i] = acc ? 1 : 0;
-    I.swaps[j] = acc ? 1 : 0;
+    if (lane == 0) {
+        if (acc) {
+            I.bin[i] = bj;
+            I.bin[j] = bi;
+            atomicAdd((unsigned long long*)&I.ex_acc[a], 1ull);
+        }
+        atomicAdd((unsigned long long*)&I.ex_prop[a], 1ull);
+        I.swaps[i] = acc ? 1 : 0;
+        I.swaps[j] = acc ? 1 : 0;
+    }
 }
 
 // ----------------------------------------------------------------- advance

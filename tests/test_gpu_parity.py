@@ -100,6 +100,7 @@ SMALL = [
     dict(model="potts", q=4, L=12, n_windows=6, m=16, overlap=(1, 2), kfinal=12, X=2000, seed=11),
     dict(model="potts", q=3, L=5, n_windows=3, m=2, kfinal=10, X=1500, seed=13),   # odd L
     dict(model="ising", L=100, n_windows=8, m=2, kfinal=8, X=2000, seed=17),     # two words per row
+    dict(model="potts", q=10, L=70, n_windows=6, m=2, kfinal=8, X=2000, seed=47),  # N > 4096: shared site map
     dict(model="potts", q=255, L=6, n_windows=2, m=8, kfinal=6, X=1000, seed=19),  # largest q
     dict(model="ising", L=4, n_windows=1, m=4, kfinal=10, X=1, seed=23),         # one window, X = 1
     dict(model="ising", L=12, n_windows=5, m=4, kfinal=10, X=700, seed=29, exchange=False),
