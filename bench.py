@@ -342,6 +342,12 @@ def ensemble_study(rw, args) -> dict:
     base = dict(Wl.single("potts100"), kfinal=args.ens_kfinal)
     if args.m:
         base["m"] = args.m
+    if args.ens_h:
+        base["n_windows"] = args.ens_h
+    if args.ens_windows == "ground-tilt":
+        base["windows"] = ground_tilt_windows(rw, base)
+        log(f"windows {len(base['windows'][0])}, widths "
+            f"{(base['windows'][1] - base['windows'][0] + 1).tolist()}")
     kws = [dict(base, seed=1 + j) for j in range(n)]
     t0 = time.perf_counter()
     g = rw.Rewl([rw.make_config(**kw) for kw in kws], tune=rw.make_tune(poll_every=50))
@@ -398,6 +404,22 @@ def ensemble_study(rw, args) -> dict:
         out["cpu_baseline"] = ensemble_cpu_baseline(kws, n, R, T, args.cpu_budget)
     log(json.dumps(out))
     return out
+
+
+def ground_tilt_windows(rw, kw):
+    """Windows narrowed towards the ground state.  Near E0 a walker's excitations
+    are b/4 isolated flipped spins (b broken bonds above the ground level), so a
+    move down is found with probability ~ b / (36 N) per attempt and, with a flat
+    histogram, about one attempt in 18 N / b is an accepted move.  A window's cost
+    is modelled as width^2 times that factor; with rho = sqrt(kappa),
+    kappa(b) = 1 + 18 N / (b + 4) below b = 2000 and constant above (where the
+    dilute picture ends), windows of equal rho-mass have equal modelled cost."""
+    cfg = rw.make_config(**kw)
+    W = rw.rewl_layout(cfg)[0]
+    N = kw["L"] ** 2
+    b = np.minimum(np.arange(W, dtype=np.float64), 2000.0)
+    rho = np.sqrt(1.0 + 18.0 * N / (b + 4.0))
+    return rw.rewl_balanced_layout(cfg, rho)
 
 
 def ensemble_cpu_baseline(kws, n, R, T, budget_s) -> dict:
@@ -478,6 +500,8 @@ def main(argv=None):
     ap.add_argument("--ens-tmin", type=float, default=0.68)
     ap.add_argument("--ens-tmax", type=float, default=0.74)
     ap.add_argument("--ens-nT", type=int, default=601)
+    ap.add_argument("--ens-h", type=int, default=0, help="--ensemble-study: number of windows (0: 77)")
+    ap.add_argument("--ens-windows", default="equal", choices=["equal", "ground-tilt"])
     ap.add_argument("--warm", action="store_true",
                     help="train the DOS network on REWL results of small systems and compare "
                          "time to converge, warm start against plain REWL, on larger targets")
