@@ -184,9 +184,14 @@ def warm_start_study(rw, args) -> dict:
              "ising24": dict(model="ising", q=2, L=24, n_windows=8, m=16),
              "potts32": dict(model="potts", q=10, L=32, n_windows=16, m=32),
              "ising48": dict(model="ising", q=2, L=48, n_windows=32, m=32),
-             "ising64": dict(model="ising", q=2, L=64, n_windows=16, m=64)}
+             "ising64": dict(model="ising", q=2, L=64, n_windows=16, m=64),
+             # the paper's Potts lattice with windows narrowed towards the ground state
+             "potts100t": dict(model="potts", q=10, L=100, n_windows=90, m=8)}
     targets = [dict(known[t], kfinal=args.kfinal, X=10000, seed=sd) for t in args.warm_targets.split(",")
                for sd in range(1, args.warm_seeds + 1)]
+    for kw in targets:
+        if kw["L"] == 100:
+            kw["windows"] = ground_tilt_windows(rw, kw)
     modes = args.warm_modes.split(",")
     out = []
     for kw in targets:
