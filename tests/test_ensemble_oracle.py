@@ -4,8 +4,9 @@ The bootstrap of Sec. II.B is pinned by what it must reproduce: exact pieces
 with arbitrary per-run constants give the exact ln g in every row, and the
 spread of a within-piece difference over resamples equals the closed-form
 bootstrap variance of a mean of n values.  The canonical averages are pinned
-by direct Boltzmann sums over every microstate of small lattices and by the
-infinite- and zero-temperature limits.
+by direct Boltzmann sums over every microstate of small lattices, by the
+infinite- and zero-temperature limits, and by Onsager's exact solution (the
+exact 64 x 64 torus DOS away from T_c).
 """
 import numpy as np
 import pytest
@@ -189,3 +190,40 @@ def test_canonical_shift_invariance(golden):
     assert np.allclose(u1, u0, rtol=1e-12, atol=1e-13)
     assert np.allclose(c1, c0, rtol=1e-9)
     assert np.allclose(f1, f0 - T * 123.0 / 256, rtol=1e-12, atol=1e-12)
+
+
+def _onsager_u(T):
+    """Onsager's internal energy per spin of the infinite square lattice (J = 1)."""
+    from scipy.special import ellipk
+    K = 1.0 / T
+    kap = 2 * np.sinh(2 * K) / np.cosh(2 * K) ** 2
+    t2 = np.tanh(2 * K) ** 2
+    return -(1 + 2 / np.pi * (2 * t2 - 1) * ellipk(kap ** 2)) / np.tanh(2 * K)
+
+
+def _onsager_f(T):
+    """Onsager's free energy per spin: -T [ln 2 + (1 / 2 pi^2) of the double integral
+    over [0, pi]^2 of ln(cosh^2 2K - sinh 2K (cos a + cos b))]."""
+    from scipy import integrate
+    K = 1.0 / T
+    g = lambda a, b: np.log(np.cosh(2 * K) ** 2 - np.sinh(2 * K) * (np.cos(a) + np.cos(b)))
+    I, _ = integrate.dblquad(g, 0, np.pi, 0, np.pi, epsabs=1e-13, epsrel=1e-13)
+    return -T * (np.log(2) + I / (2 * np.pi ** 2))
+
+
+def test_canonical_of_exact_L64_matches_onsager(golden):
+    """Away from T_c a 64 x 64 torus is the infinite lattice up to terms ~ e^{-L/xi}:
+    u equals Onsager's closed form, c its temperature derivative, and f Onsager's
+    free energy above T_c; below T_c the two ordered states of the finite torus add
+    -T ln 2 / N to f."""
+    lg = golden.lng("ising_L64_lng.txt")
+    N = 64 * 64
+    T = np.array([1.0, 1.5, 1.8, 3.0, 4.0, 6.0])
+    u, c, f = EN.canonical("ising", 64, lg, T)
+    assert np.max(np.abs(u - _onsager_u(T))) < 1e-12
+    h = 1e-4
+    dudT = (_onsager_u(T + h) - _onsager_u(T - h)) / (2 * h)
+    assert np.max(np.abs(c / dudT - 1)) < 1e-6
+    for i, t in enumerate(T):
+        shift = -t * np.log(2) / N if t < 2.269 else 0.0
+        assert abs(f[i] - (_onsager_f(t) + shift)) < 1e-9
