@@ -24,3 +24,24 @@ def test_profiled_traffic_requires_matching_sources(monkeypatch):
     assert got is None or (len(got) == 2 and all(v > 0 for v in got))
     assert bench.profiled_traffic("ising64", "no_such_kernel") is None
     assert bench.profiled_traffic("batch64", "k_sweep") is None
+
+
+def test_ground_tilted_windows_are_a_valid_layout():
+    """The windows narrowed towards the ground state for the L = 100 Potts runs
+    (pure host): accepted by the oracle's layout check, narrowest at the ground
+    level, widening up to b ~ 2000 and even above it."""
+    sys.path.insert(0, ROOT)
+    import numpy as np
+    import bench
+    import oracle as O
+    import paper_1407_5140_amd as rw
+    kw = dict(model="potts", q=10, L=100, n_windows=90, m=8, kfinal=14, X=10000, seed=1)
+    lo, hi = bench.ground_tilt_windows(rw, kw)
+    c = O.make_config(**dict(kw, windows=(lo, hi)))
+    olo, ohi = O.layout(c)
+    assert np.array_equal(olo, lo) and np.array_equal(ohi, hi)
+    w = hi - lo + 1
+    assert lo[0] == 0 and hi[-1] == 2 * 100 * 100
+    assert w[0] < 200 and np.all(np.diff(w[:8]) > 0)
+    upper = w[lo > 2000]
+    assert upper.max() - upper.min() <= 2 and upper.max() < 1001
