@@ -81,7 +81,8 @@ enum { REWL_FLAT_MEAN = 0, REWL_FLAT_VISITS = 1 };
  * interval by a separate kernel (suits batches of many thousands of walkers).
  * WAVE: one walker per wave, the chain on wave-uniform values, the lanes draw
  * the next 64 attempts (suits few walkers; falls back to LANE where one walker's
- * wave tables do not fit the LDS).                                               */
+ * wave tables do not fit the LDS).  AUTO: WAVE for a batch of at most 8192
+ * walkers in all, LANE above that.  Both give bit-identical results.            */
 enum { REWL_SWEEP_AUTO = 0, REWL_SWEEP_LANE = 1, REWL_SWEEP_WAVE = 2 };
 
 /* Optional tuning of a batch (NULL = library choice). */
