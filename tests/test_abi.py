@@ -128,3 +128,17 @@ def test_thermo_and_ensemble_validate_on_the_host(rw):
     with pytest.raises(rw.RewlError) as e:
         rw.rewl_ensemble(None, [0], 1, 1, 17, 4)
     assert e.value.status == rw.REWL_E_INVALID
+
+
+def test_import_without_the_library_fails_loudly(tmp_path):
+    """No CPU fallback: the binding refuses to import when librewl.so is absent."""
+    import shutil
+    import subprocess
+    import sys
+    pkg = tmp_path / "paper_1407_5140_amd"
+    pkg.mkdir()
+    shutil.copy(os.path.join(ROOT, "paper_1407_5140_amd", "__init__.py"), pkg / "__init__.py")
+    r = subprocess.run([sys.executable, "-c", "import paper_1407_5140_amd"], cwd=tmp_path,
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0
+    assert "ImportError" in r.stderr and "no CPU fallback" in r.stderr
