@@ -1,7 +1,7 @@
 """Exact densities of states g(E) for the periodic 2D Ising and q-state Potts models.
 
 TEST INFRASTRUCTURE ONLY (part of the oracle).  These exact counts pin the REWL
-oracle and judge the accuracy of its estimates; the product never imports them.
+oracle and measure the accuracy of its estimates; the product never imports them.
 
 Three independent routes, each exact in integer arithmetic:
 
