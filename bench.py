@@ -417,14 +417,28 @@ def ground_tilt_windows(rw, kw):
     move down is found with probability ~ b / (36 N) per attempt and, with a flat
     histogram, about one attempt in 18 N / b is an accepted move.  A window's cost
     is modelled as width^2 times that factor; with rho = sqrt(kappa),
-    kappa(b) = 1 + 18 N / (b + 4) below b = 2000 and constant above (where the
+    kappa(b) = 1 + 18 N / (b + 4) below b = N/5 and constant above (where the
     dilute picture ends), windows of equal rho-mass have equal modelled cost."""
     cfg = rw.make_config(**kw)
     W = rw.rewl_layout(cfg)[0]
     N = kw["L"] ** 2
-    b = np.minimum(np.arange(W, dtype=np.float64), 2000.0)
+    b = np.minimum(np.arange(W, dtype=np.float64), N / 5)
     rho = np.sqrt(1.0 + 18.0 * N / (b + 4.0))
     return rw.rewl_balanced_layout(cfg, rho)
+
+
+def end_tilt_windows(rw, kw):
+    """Ising windows narrowed towards both ends of the range (the ferromagnetic and
+    the antiferromagnetic ground levels).  Near an end a configuration holds about
+    d/2 isolated flipped spins (d bins from the end, a flip costs two bins), so about
+    one attempt in N/d is an accepted move; kappa(d) = 1 + N/(d + 2) up to d = N/5,
+    rho = sqrt(kappa), windows of equal rho-mass (the model of ground_tilt_windows)."""
+    cfg = rw.make_config(**kw)
+    W = rw.rewl_layout(cfg)[0]
+    N = kw["L"] ** 2
+    b = np.arange(W, dtype=np.float64)
+    d = np.minimum(np.minimum(b, W - 1 - b), N / 5)
+    return rw.rewl_balanced_layout(cfg, np.sqrt(1.0 + N / (d + 2.0)))
 
 
 def ensemble_cpu_baseline(kws, n, R, T, budget_s) -> dict:
@@ -485,6 +499,8 @@ def main(argv=None):
     ap.add_argument("--flat", default="", help="--converge: flatness parameter num,den")
     ap.add_argument("--m", type=int, default=0, help="--converge: walkers per window override")
     ap.add_argument("--kfinal-override", type=int, default=0, help="--converge: final ln f exponent")
+    ap.add_argument("--windows", default="equal", choices=["equal", "tilted"],
+                    help="--converge: tilted = narrowed towards the slow ends (Ising both, Potts the ground level)")
     ap.add_argument("--mlp-bench", action="store_true", help="time the DOS network's training steps")
     ap.add_argument("--mlp-warmup-steps", type=int, default=20)
     ap.add_argument("--balanced-study", action="store_true",
@@ -566,7 +582,11 @@ def main(argv=None):
             kw["m"] = args.m
         if args.kfinal_override:
             kw["kfinal"] = args.kfinal_override
+        if args.windows != "equal":
+            kw["windows"] = (end_tilt_windows if kw["model"] == "ising" else ground_tilt_windows)(rw, kw)
         label += f"; flatness {kw['flat_rule']} {kw.get('flat', (4, 5))}, m={kw['m']}, kfinal={kw['kfinal']}"
+        if args.windows != "equal":
+            label += f"; windows {args.windows} {(kw['windows'][1] - kw['windows'][0] + 1).tolist()}"
         for sd in [int(x) for x in args.seeds.split(",")]:
             print(json.dumps(converge(rw, kw, label, tune, args.max_seconds, sd)), flush=True)
         return 0
