@@ -191,7 +191,7 @@ def warm_start_study(rw, args) -> dict:
                for sd in range(1, args.warm_seeds + 1)]
     for kw in targets:
         if kw["L"] == 100:
-            kw["windows"] = ground_tilt_windows(rw, kw)
+            kw["windows"] = tilted_windows(rw, kw)
     modes = args.warm_modes.split(",")
     out = []
     for kw in targets:
@@ -350,7 +350,7 @@ def ensemble_study(rw, args) -> dict:
     if args.ens_h:
         base["n_windows"] = args.ens_h
     if args.ens_windows == "ground-tilt":
-        base["windows"] = ground_tilt_windows(rw, base)
+        base["windows"] = tilted_windows(rw, base)
         log(f"windows {len(base['windows'][0])}, widths "
             f"{(base['windows'][1] - base['windows'][0] + 1).tolist()}")
     kws = [dict(base, seed=1 + j) for j in range(n)]
@@ -411,34 +411,10 @@ def ensemble_study(rw, args) -> dict:
     return out
 
 
-def ground_tilt_windows(rw, kw):
-    """Windows narrowed towards the ground state.  Near E0 a walker's excitations
-    are b/4 isolated flipped spins (b broken bonds above the ground level), so a
-    move down is found with probability ~ b / (36 N) per attempt and, with a flat
-    histogram, about one attempt in 18 N / b is an accepted move.  A window's cost
-    is modelled as width^2 times that factor; with rho = sqrt(kappa),
-    kappa(b) = 1 + 18 N / (b + 4) below b = N/5 and constant above (where the
-    dilute picture ends), windows of equal rho-mass have equal modelled cost."""
-    cfg = rw.make_config(**kw)
-    W = rw.rewl_layout(cfg)[0]
-    N = kw["L"] ** 2
-    b = np.minimum(np.arange(W, dtype=np.float64), N / 5)
-    rho = np.sqrt(1.0 + 18.0 * N / (b + 4.0))
-    return rw.rewl_balanced_layout(cfg, rho)
-
-
-def end_tilt_windows(rw, kw):
-    """Ising windows narrowed towards both ends of the range (the ferromagnetic and
-    the antiferromagnetic ground levels).  Near an end a configuration holds about
-    d/2 isolated flipped spins (d bins from the end, a flip costs two bins), so about
-    one attempt in N/d is an accepted move; kappa(d) = 1 + N/(d + 2) up to d = N/5,
-    rho = sqrt(kappa), windows of equal rho-mass (the model of ground_tilt_windows)."""
-    cfg = rw.make_config(**kw)
-    W = rw.rewl_layout(cfg)[0]
-    N = kw["L"] ** 2
-    b = np.arange(W, dtype=np.float64)
-    d = np.minimum(np.minimum(b, W - 1 - b), N / 5)
-    return rw.rewl_balanced_layout(cfg, np.sqrt(1.0 + N / (d + 2.0)))
+def tilted_windows(rw, kw):
+    """Windows narrowed towards the slow ground levels: the library's difficulty
+    model near the ground levels (rewl_tilt_density) through rewl_balanced_layout."""
+    return rw.tilted_layout(rw.make_config(**kw))
 
 
 def ensemble_cpu_baseline(kws, n, R, T, budget_s) -> dict:
@@ -583,7 +559,7 @@ def main(argv=None):
         if args.kfinal_override:
             kw["kfinal"] = args.kfinal_override
         if args.windows != "equal":
-            kw["windows"] = (end_tilt_windows if kw["model"] == "ising" else ground_tilt_windows)(rw, kw)
+            kw["windows"] = tilted_windows(rw, kw)
         label += f"; flatness {kw['flat_rule']} {kw.get('flat', (4, 5))}, m={kw['m']}, kfinal={kw['kfinal']}"
         if args.windows != "equal":
             label += f"; windows {args.windows} {(kw['windows'][1] - kw['windows'][0] + 1).tolist()}"

@@ -119,6 +119,20 @@ rewl_status rewl_layout(const rewl_config* cfg, int32_t* n_bins, int32_t* window
  * receive inclusive global bins valid as the config's explicit windows.          */
 rewl_status rewl_balanced_layout(const rewl_config* cfg, const double* rho, int32_t* lo, int32_t* hi);
 
+/* Pure host: a difficulty density for rewl_balanced_layout from a model of the
+ * single-spin-flip walk near the ground levels, where a walker spends most
+ * attempts on rejected moves (the slow end windows that Sec. V proposes to
+ * narrow).  Near a ground level a configuration holds a dilute set of flipped
+ * spins, so only about one attempt in kappa is an accepted move:
+ *   Ising: kappa = 1 + N / (d + 2), d = bins to the nearer end (both the ferro-
+ *          and the antiferromagnetic ground level; a flip costs two bins);
+ *   Potts: kappa = 1 + 18 N / (b + 4), b = bins above the ground level (a flip
+ *          back to the surrounding state is 1 of N sites times 1 of q - 1 states);
+ * with d and b capped at N/5, where the dilute picture ends.  A window's cost is
+ * modelled as width^2 kappa, so rho[b] = sqrt(kappa) (W entries) makes windows of
+ * equal rho-mass equally costly.                                                 */
+rewl_status rewl_tilt_density(const rewl_config* cfg, double* rho);
+
 /* Pure host: mask[W] = 1 where the energy level occurs on the periodic lattice. */
 rewl_status rewl_mask(const rewl_config* cfg, uint8_t* mask);
 

@@ -73,6 +73,7 @@ _sigs = {
     "rewl_layout": ([_P(rewl_config), _vp, _vp, _vp, _vp], ctypes.c_int),
     "rewl_mask": ([_P(rewl_config), _vp], ctypes.c_int),
     "rewl_balanced_layout": ([_P(rewl_config), _vp, _vp, _vp], ctypes.c_int),
+    "rewl_tilt_density": ([_P(rewl_config), _vp], ctypes.c_int),
     "rewl_create": ([_P(rewl_config), _vp, _P(_vp)], ctypes.c_int),
     "rewl_batch_create": ([_P(rewl_config), ctypes.c_int32, _vp, _P(rewl_tune), _P(_vp)], ctypes.c_int),
     "rewl_set_initial_lng": ([_vp, ctypes.c_int32, _vp], ctypes.c_int),
@@ -175,6 +176,18 @@ def rewl_balanced_layout(cfg: rewl_config, rho) -> tuple[np.ndarray, np.ndarray]
     hi = np.zeros(cfg.n_windows, np.int32)
     _check(_lib.rewl_balanced_layout(ctypes.byref(cfg), _p(r), _p(lo), _p(hi)), "rewl_balanced_layout")
     return lo, hi
+
+
+def rewl_tilt_density(cfg: rewl_config) -> np.ndarray:
+    """Difficulty density near the ground levels, for rewl_balanced_layout (pure host)."""
+    rho = np.zeros(rewl_layout(cfg)[0], np.float64)
+    _check(_lib.rewl_tilt_density(ctypes.byref(cfg), _p(rho)), "rewl_tilt_density")
+    return rho
+
+
+def tilted_layout(cfg: rewl_config) -> tuple[np.ndarray, np.ndarray]:
+    """Windows narrowed towards the slow ground levels (pure host)."""
+    return rewl_balanced_layout(cfg, rewl_tilt_density(cfg))
 
 
 def rewl_mask(cfg: rewl_config) -> np.ndarray:

@@ -333,6 +333,28 @@ rewl_status rewl_layout(const rewl_config* cfg, int32_t* n_bins, int32_t* window
     return REWL_OK;
 }
 
+rewl_status rewl_tilt_density(const rewl_config* cfg, double* rho)
+{
+    if (!cfg || !rho) return fail(REWL_E_INVALID, "null argument");
+    rewl_config c = *cfg;
+    c.window_lo = c.window_hi = nullptr;
+    rewl_status st = validate(c);
+    if (st != REWL_OK) return st;
+    const double N = (double)c.L * c.L, cap = N / 5.0;
+    const int W = c.model == 0 ? c.L * c.L + 1 : 2 * c.L * c.L + 1;
+    for (int b = 0; b < W; ++b) {
+        double kappa;
+        if (c.model == 0) {
+            const double d = std::min({(double)b, (double)(W - 1 - b), cap});
+            kappa = 1.0 + N / (d + 2.0);
+        } else {
+            kappa = 1.0 + 18.0 * N / (std::min((double)b, cap) + 4.0);
+        }
+        rho[b] = std::sqrt(kappa);
+    }
+    return REWL_OK;
+}
+
 rewl_status rewl_balanced_layout(const rewl_config* cfg, const double* rho, int32_t* lo, int32_t* hi)
 {
     if (!cfg || !rho || !lo || !hi) return fail(REWL_E_INVALID, "null argument");

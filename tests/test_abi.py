@@ -142,3 +142,25 @@ def test_import_without_the_library_fails_loudly(tmp_path):
                        capture_output=True, text=True, timeout=120)
     assert r.returncode != 0
     assert "ImportError" in r.stderr and "no CPU fallback" in r.stderr
+
+
+def test_tilt_density_model(rw):
+    """rewl_tilt_density: sqrt of the rejected-move factor near the ground levels
+    (Ising both ends, symmetric; Potts the ground end), flat beyond N/5."""
+    ci = rw.make_config(model="ising", L=16, n_windows=4)
+    r = rw.rewl_tilt_density(ci)
+    N = 256
+    assert r.size == N + 1 and np.allclose(r, r[::-1])
+    assert np.isclose(r[0], np.sqrt(1 + N / 2)) and np.isclose(r[10], np.sqrt(1 + N / 12))
+    assert np.allclose(r[52:N - 51], np.sqrt(1 + N / (N / 5 + 2)))
+    cp = rw.make_config(model="potts", q=10, L=20, n_windows=6)
+    r = rw.rewl_tilt_density(cp)
+    N = 400
+    assert r.size == 2 * N + 1
+    assert np.isclose(r[0], np.sqrt(1 + 18 * N / 4)) and np.isclose(r[36], np.sqrt(1 + 18 * N / 40))
+    assert np.all(np.diff(r[:81]) < 0) and np.allclose(r[80:], np.sqrt(1 + 18 * N / 84))
+    lo, hi = rw.tilted_layout(cp)
+    w = hi - lo + 1
+    assert w[0] < w[-1] and lo[0] == 0 and hi[-1] == 2 * N
+    with pytest.raises(rw.RewlError):
+        rw.rewl_tilt_density(rw.make_config(model="ising", L=16, n_windows=0))

@@ -36,7 +36,7 @@ def test_ground_tilted_windows_are_a_valid_layout():
     import oracle as O
     import paper_1407_5140_amd as rw
     kw = dict(model="potts", q=10, L=100, n_windows=90, m=8, kfinal=14, X=10000, seed=1)
-    lo, hi = bench.ground_tilt_windows(rw, kw)
+    lo, hi = bench.tilted_windows(rw, kw)
     c = O.make_config(**dict(kw, windows=(lo, hi)))
     olo, ohi = O.layout(c)
     assert np.array_equal(olo, lo) and np.array_equal(ohi, hi)
