@@ -222,6 +222,42 @@ def warm_start_study(rw, args) -> dict:
             "network": info, "targets": out}
 
 
+def warm_error_study(rw, args) -> dict:
+    """How accurate a starting table must be for a given initial ln f = 2^-k0:
+    a converged run (ln f -> 2^-20) of 10-state Potts L=16 serves as the true
+    table; warm tables are that table plus a smooth error of amplitude delta
+    (three periods of a sine over the energy range, rounded to 2^-16), and each
+    (delta, k0) pair runs to 2^-kfinal on the same seed.  Counted in intervals."""
+    from paper_1407_5140_amd import warm as Wm
+    log = lambda m: print(f"[warm-error] {m}", file=sys.stderr, flush=True)
+    kw = dict(model="potts", q=10, L=16, n_windows=4, m=8, X=2000, seed=3)
+    g, res = Wm.run_to_convergence([dict(kw, kfinal=20)], args.max_seconds, poll=10)
+    truth, _ = g.concat(0)
+    g.close()
+    W = truth.size
+    b = np.arange(W)
+    base = np.where(np.isfinite(truth), truth, 0.0)
+    out = {"mode": "warm-table error against initial ln f", "workload": "2D 10-state Potts L=16, h=4, m=8, "
+           f"X=2000, ln f -> 2^-{args.kfinal}", "reference_intervals": res[0]["intervals"], "runs": []}
+    plain = None
+    for delta in [float(v) for v in args.error_deltas.split(",")]:
+        tab = base + delta * np.sin(6 * np.pi * b / (W - 1))
+        tab = np.round(tab * 65536.0) / 65536.0
+        for k0 in [int(v) for v in args.error_k0s.split(",")]:
+            k = dict(kw, kfinal=args.kfinal, k0=k0)
+            gg, rr = Wm.run_to_convergence([k], args.target_seconds, warm_tables=[tab], poll=10)
+            gg.close()
+            r = {"delta": delta, "k0": k0, "converged": rr[0]["converged"], "intervals": rr[0]["intervals"],
+                 "seconds": rr[0]["seconds"]}
+            out["runs"].append(r)
+            log(str(r))
+    gg, rr = Wm.run_to_convergence([dict(kw, kfinal=args.kfinal)], args.target_seconds, poll=10)
+    gg.close()
+    out["plain"] = {"intervals": rr[0]["intervals"], "seconds": rr[0]["seconds"], "converged": rr[0]["converged"]}
+    log(f"plain: {out['plain']}")
+    return out
+
+
 def exchange_study(rw, args) -> dict:
     """Replica exchange on against off, and the exchange interval, on the paper's
     kind of test (Sec. IV: a Potts model split into 15 windows): attempts per
@@ -484,6 +520,10 @@ def main(argv=None):
     ap.add_argument("--study-L-balanced", type=int, default=32)
     ap.add_argument("--kfinal-balanced", type=int, default=20)
     ap.add_argument("--k-pilot", type=int, default=12)
+    ap.add_argument("--warm-error-study", action="store_true",
+                    help="intervals to converge from tables of known error against the initial ln f")
+    ap.add_argument("--error-deltas", default="0.1,1,10")
+    ap.add_argument("--error-k0s", default="0,6,10")
     ap.add_argument("--exchange-study", action="store_true",
                     help="attempts to converge with replica exchange on/off and several intervals")
     ap.add_argument("--study-L", type=int, default=24)
@@ -537,6 +577,9 @@ def main(argv=None):
         return 0
     if args.mlp_bench:
         print(json.dumps(mlp_bench(rw, args)), flush=True)
+        return 0
+    if args.warm_error_study:
+        print(json.dumps(warm_error_study(rw, args)), flush=True)
         return 0
     if args.exchange_study:
         print(json.dumps(exchange_study(rw, args)), flush=True)
