@@ -197,10 +197,11 @@ def warm_start_study(rw, args) -> dict:
     for kw in targets:
         label = f"{kw['model']} q={kw['q']} L={kw['L']} h={kw['n_windows']} m={kw['m']} seed={kw['seed']}"
         tab = Wm.warm_table(net, kw)
-        row = {"workload": label, "kfinal": kw["kfinal"], "k0_warm": args.k0}
+        k0 = args.k0 if args.k0 >= 0 else Wm.suggest_k0(info["rms"], kw["L"] ** 2)
+        row = {"workload": label, "kfinal": kw["kfinal"], "k0_warm": k0}
         ex = exact_ln_g(kw)
         for mode in modes:
-            k = dict(kw, k0=args.k0 if mode == "warm" else 0)
+            k = dict(kw, k0=k0 if mode == "warm" else 0)
             gg, rr = Wm.run_to_convergence([k], args.target_seconds,
                                            warm_tables=[tab] if mode == "warm" else None, log=log)
             r = dict(rr[0])
@@ -550,7 +551,8 @@ def main(argv=None):
     ap.add_argument("--warm-targets", default="potts32,ising48")
     ap.add_argument("--warm-modes", default="warm,plain")
     ap.add_argument("--kfinal", type=int, default=18, help="--warm: targets' final ln f = 2^-kfinal")
-    ap.add_argument("--k0", type=int, default=10, help="--warm: warm start's initial ln f = 2^-k0")
+    ap.add_argument("--k0", type=int, default=10,
+                    help="--warm: warm start's initial ln f = 2^-k0 (-1: from the network's error)")
     ap.add_argument("--mlp-steps", type=int, default=4000)
     ap.add_argument("--target-seconds", type=float, default=200.0)
     args = ap.parse_args(argv)

@@ -120,3 +120,15 @@ def train(x, t, steps: int = 4000, batch: int = 4096, lr: float = 1e-3, seed: in
 
 def warm_table(net: Mlp, kw: dict) -> np.ndarray:
     return net.warm_table(kw["model"], kw["q"], kw["L"])
+
+
+def suggest_k0(rms_s: float, N: int, k_max: int = 10) -> int:
+    """Initial ln f = 2^-k0 for a warm table whose error in ln g/N is about rms_s.
+
+    The table's error in ln g is about delta = rms_s N.  Measured on 10-state Potts
+    L=16 with smooth table errors of known size: up to delta ~ 1 a start at 2^-10
+    needs a third of plain WL's intervals, and at delta = 10 a start at 2^-6 beats
+    one at 2^-10.  So k0 = k_max - log2(delta) for delta > 1, floored, within
+    0..k_max."""
+    delta = max(float(rms_s) * float(N), 1.0)
+    return int(min(k_max, max(0, np.floor(k_max - np.log2(delta)))))

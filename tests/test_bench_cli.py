@@ -45,3 +45,13 @@ def test_ground_tilted_windows_are_a_valid_layout():
     assert w[0] < 200 and np.all(np.diff(w[:8]) > 0)
     upper = w[lo > 2000]
     assert upper.max() - upper.min() <= 2 and upper.max() < 1001
+
+
+def test_suggested_k0_follows_the_table_error():
+    sys.path.insert(0, ROOT)
+    from paper_1407_5140_amd import warm as Wm
+    assert Wm.suggest_k0(1e-5, 1024) == 10          # error ~0.01 in ln g: the full skip
+    assert Wm.suggest_k0(9e-4, 1024) == 10          # just below 1
+    assert Wm.suggest_k0(1e-2, 1024) == 6           # ~10: the measured better start
+    assert Wm.suggest_k0(3.8e-3, 10000) == 4        # the L = 100 network, ~38
+    assert Wm.suggest_k0(1.0, 10 ** 6) == 0
