@@ -893,25 +893,20 @@ rewl_status rewl_concat(rewl_handle* H, int32_t i, double* out_lng, int32_t* joi
     if (s != REWL_OK) return s;
     if (!out_lng) return fail(REWL_E_INVALID, "null output");
     HostInst& hi = H->inst[i];
-    double *d_out = nullptr, *d_shift = nullptr;
-    int32_t *d_join = nullptr, *d_status = nullptr;
-    HIP_TRY(hipMalloc(&d_out, hi.W * 8));
-    HIP_TRY(hipMalloc(&d_shift, hi.h * 8));
-    HIP_TRY(hipMalloc(&d_join, std::max(hi.h - 1, 1) * 4));
-    HIP_TRY(hipMalloc(&d_status, 4));
-    hipLaunchKernelGGL(k_concat, dim3(1), dim3(256), 0, H->stream, H->d_insts, i, hi.dev.base, d_out,
-                       d_join, d_shift, d_status);
     int32_t status = 0;
+    DevBuf d_out, d_shift, d_join, d_status;       // released (after the device is idle) on every return
+    HIP_TRY(d_out.alloc((size_t)hi.W * 8));
+    HIP_TRY(d_shift.alloc((size_t)hi.h * 8));
+    HIP_TRY(d_join.alloc((size_t)std::max(hi.h - 1, 1) * 4));
+    HIP_TRY(d_status.alloc(4));
+    hipLaunchKernelGGL(k_concat, dim3(1), dim3(256), 0, H->stream, H->d_insts, i, hi.dev.base,
+                       d_out.as<double>(), d_join.as<int32_t>(), d_shift.as<double>(), d_status.as<int32_t>());
     hipError_t e = hipGetLastError();
-    if (e == hipSuccess) e = hipMemcpyAsync(out_lng, d_out, hi.W * 8, hipMemcpyDeviceToHost, H->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(out_lng, d_out.p, (size_t)hi.W * 8, hipMemcpyDeviceToHost, H->stream);
     if (e == hipSuccess && join && hi.h > 1)
-        e = hipMemcpyAsync(join, d_join, (hi.h - 1) * 4, hipMemcpyDeviceToHost, H->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(&status, d_status, 4, hipMemcpyDeviceToHost, H->stream);
+        e = hipMemcpyAsync(join, d_join.p, (size_t)(hi.h - 1) * 4, hipMemcpyDeviceToHost, H->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&status, d_status.p, 4, hipMemcpyDeviceToHost, H->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(H->stream);
-    (void)hipFree(d_out);
-    (void)hipFree(d_shift);
-    (void)hipFree(d_join);
-    (void)hipFree(d_status);
     if (e != hipSuccess) return fail(REWL_E_DEVICE, std::string("concat: ") + hipGetErrorString(e));
     if (status != 0) return fail(REWL_E_STATE, "no valid join point in some overlap");
     return REWL_OK;
@@ -942,6 +937,9 @@ rewl_status rewl_ensemble(rewl_handle* H, const int32_t* runs, int32_t n, int32_
         return fail(REWL_E_INVALID, "ensemble tables exceed 16 GiB: use fewer resamples per call");
     std::vector<const double*> ptrs(n);
     for (int j = 0; j < n; ++j) ptrs[j] = H->inst[runs[j]].dev.base;
+    // host staging first: on an early return the device buffers are released
+    // (hipFree waits for the device) before these go out of scope
+    std::vector<int32_t> status(rows), jall(join && h > 1 ? rows * nj : 0);
     DevBuf d_ptrs, d_mean, d_out, d_join, d_shift, d_status;
     HIP_TRY(d_ptrs.alloc(n * sizeof(double*)));
     HIP_TRY(d_mean.alloc(mean_b));
@@ -958,12 +956,9 @@ rewl_status rewl_ensemble(rewl_handle* H, const int32_t* runs, int32_t n, int32_
                        d_mean.as<double>(), d_out.as<double>(), d_join.as<int32_t>(),
                        d_shift.as<double>(), d_status.as<int32_t>());
     HIP_TRY(hipGetLastError());
-    std::vector<int32_t> status(rows), jall;
     HIP_TRY(hipMemcpyAsync(out_lng, d_out.p, out_b, hipMemcpyDeviceToHost, H->stream));
-    if (join && h > 1) {
-        jall.resize(rows * nj);
+    if (join && h > 1)
         HIP_TRY(hipMemcpyAsync(jall.data(), d_join.p, rows * nj * 4, hipMemcpyDeviceToHost, H->stream));
-    }
     HIP_TRY(hipMemcpyAsync(status.data(), d_status.p, rows * 4, hipMemcpyDeviceToHost, H->stream));
     HIP_TRY(hipStreamSynchronize(H->stream));
     if (join && h > 1) std::memcpy(join, jall.data(), rows * nj * 4);
