@@ -34,7 +34,11 @@ typedef enum {
     REWL_E_EMPTY_WINDOW = -2, /* a window holds no energy level that occurs         */
     REWL_E_NOMEM = -3,        /* device or host allocation failed                  */
     REWL_E_DEVICE = -4,       /* a HIP call failed                                  */
-    REWL_E_OVERFLOW = -5,     /* a histogram or the exact-FP64 budget would overflow */
+    REWL_E_OVERFLOW = -5,     /* the exact-FP64 budget would overflow, or a walker's
+                                 counts since its last merge spread over more than
+                                 2^32 - X (its highest count minus its lowest over the
+                                 levels of its window that occur: a walker stuck on a
+                                 few levels); the handle's state is then undefined   */
     REWL_E_INIT_STUCK = -6,   /* a walker could not be driven into its window       */
     REWL_E_STATE = -7         /* call not valid in the handle's current state       */
 } rewl_status;
@@ -96,6 +100,11 @@ typedef struct {
                                    so blocks per CU); 0 = the device limit               */
     int32_t autotune;           /* 1: time candidate variants / LDS targets on the real
                                    batch for two intervals at creation, keep the fastest */
+    int32_t guard_band_log2;    /* guard band of the fast acceptance test, 2^v:
+                                   0 = 2^-40 (the default); -40..-2 widen it.  Every
+                                   decision stays exact either way; a wider band only
+                                   sends more of them to the exact slow path (used by
+                                   the tests to exercise that path).                  */
 } rewl_tune;
 
 typedef struct rewl_handle rewl_handle;
@@ -203,10 +212,11 @@ rewl_status rewl_thermo(int32_t model, int32_t L, const double* lng, int32_t S, 
                         int32_t nT, double* u, double* c, double* f);
 
 /* Full state of one instance for inspection (S = h*m slots, slot = a*m + r):
- *   spins[S*N] (Ising 1 = up; Potts 0..q-1), bins[S], H[S*WB], lng[S*WB]
- *   (each walker's ln g), flat[S], k[h], done[h], swaps[S] (1 exchanged in the
- *   last interval, 0 proposed and rejected, -1 not proposed), *t = completed
- *   intervals.  Any pointer may be NULL.                                        */
+ *   spins[S*N] (Ising 1 = up; Potts 0..q-1), bins[S], H[S*WB] (each walker's
+ *   counts since its window's last merge: 64-bit, no ceiling below 2^53),
+ *   lng[S*WB] (each walker's ln g), flat[S], k[h], done[h], swaps[S] (1
+ *   exchanged in the last interval, 0 proposed and rejected, -1 not proposed),
+ *   *t = completed intervals.  Any pointer may be NULL.                         */
 rewl_status rewl_get_state(rewl_handle* h, int32_t instance, uint8_t* spins, int32_t* bins,
                            int64_t* H, double* lng, uint8_t* flat, int32_t* k, uint8_t* done,
                            int8_t* swaps, int64_t* t);
@@ -218,12 +228,25 @@ typedef struct {
     int32_t min_k;              /* smallest ln f exponent over windows                 */
     double sweep_ms;            /* summed device time of the sweep launches (events)   */
     double interval_ms;         /* summed device time of whole intervals (events)      */
+    int64_t round_trips;        /* completed replica round trips, all replicas          */
+    int64_t slow_decisions;     /* acceptance decisions (moves and exchanges) that fell
+                                   inside the guard band and were taken exactly by the
+                                   slow path                                            */
 } rewl_stats;
 
-/* Counters of one instance; ex_prop/ex_acc (h entries each, may be NULL):
- * proposed and accepted exchanges per window pair (a, a+1).                     */
+/* Counters of one instance.  Each may be NULL:
+ *   ex_prop, ex_acc (h entries): proposed and accepted exchanges per window pair
+ *     (a, a+1) (Eq. (1));
+ *   k (h entries): each window's current ln f exponent, ln f = 2^-k;
+ *   round_trips (S = h*m entries, by replica): completed round trips of each
+ *     replica over the energy range, the diagnostic of Sec. IV.A
+ *     (fig:wanderlogs).  A replica is a configuration, identified by the slot it
+ *     started in (replica r starts in slot r = a*m + w); it moves one window per
+ *     accepted exchange.  A round trip is a visit to window 0, then to window
+ *     h-1, then to window 0 again (a replica starting in window 0 has made the
+ *     first visit); none are counted for h = 1.                                  */
 rewl_status rewl_get_stats(rewl_handle* h, int32_t instance, rewl_stats* out, int64_t* ex_prop,
-                           int64_t* ex_acc);
+                           int64_t* ex_acc, int32_t* k, int32_t* round_trips);
 
 /* Enable (1) or disable (0) per-launch event timing of the sweep kernel. */
 rewl_status rewl_set_timing(rewl_handle* h, int32_t on);

@@ -99,6 +99,9 @@ def lib():
         L.orc_boot_picks.argtypes = [ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                      ctypes.c_void_p]
         L.orc_boot_picks.restype = ctypes.c_int
+        L.orc_replicas.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        L.orc_set_tables.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        L.orc_test_exchange_mutation.argtypes = [ctypes.c_int]
         _lib = L
     return _lib
 
@@ -231,3 +234,24 @@ class Sim:
 
     def init_attempts_max(self) -> int:
         return int(lib().orc_init_attempts_max(self.h))
+
+    def replicas(self) -> dict:
+        """rid[S]: replica held by each slot; round_trips[S]: completed round trips
+        0 -> h-1 -> 0 of each replica (Sec. IV.A)."""
+        rid = np.empty(self.S, np.int32)
+        rt = np.empty(self.S, np.int32)
+        lib().orc_replicas(self.h, _ptr(rid), _ptr(rt))
+        return dict(rid=rid, round_trips=rt)
+
+    def set_tables(self, H=None, lng=None) -> None:
+        """Replace every walker's counts and ln g (S x WB each)."""
+        h = None if H is None else np.ascontiguousarray(H, dtype=np.int64)
+        g = None if lng is None else np.ascontiguousarray(lng, dtype=np.float64)
+        for a in (h, g):
+            assert a is None or a.shape == (self.S, self.WB)
+        lib().orc_set_tables(self.h, None if h is None else _ptr(h), None if g is None else _ptr(g))
+
+
+def exchange_mutation(mode: int) -> None:
+    """Test hook: plant a mistake in the oracle's exchange rule (0 restores Eq. (1))."""
+    lib().orc_test_exchange_mutation(int(mode))

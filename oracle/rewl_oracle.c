@@ -25,7 +25,10 @@
  *   R12 pairing between neighbour windows: r <-> (r + c) mod m, c random;
  *   R13 no WL update on exchange;
  *   R14 concatenation stencil step clamp(overlap/8, 1, 10), ties to low E,
- *       each join searched above the previous one so that pieces stay in order.
+ *       each join searched above the previous one so that pieces stay in order;
+ *   R29 replica round trips (Sec. IV.A, fig:wanderlogs): a replica is a
+ *       configuration; it moves one window per accepted exchange; a round trip
+ *       is a visit to window 0, then to window h-1, then to window 0 again.
  */
 #include "rewl_oracle.h"
 
@@ -198,9 +201,20 @@ struct orc_sim {
     int8_t* swaps;    /* S    */
     int64_t t, attempts;
     int64_t *ex_prop, *ex_acc;
+    int32_t* rid;     /* S: replica held by each slot                         */
+    int8_t* rt_state; /* S, by replica: 0 window 0 not yet visited, 1 visited,  */
+                      /*    2 window h-1 reached after the last visit to 0      */
+    int32_t* rt_count;/* S, by replica: completed round trips                  */
     int all_done, init_max, error;
     uint32_t key[2];
 };
+
+/* Test hook: planted mistakes in the exchange rule, so that the tests can show */
+/* that their checks of Eq. (1) fail on a wrong rule.  0 = Eq. (1) as written;  */
+/* 1 = accept every proposal whose energies fit both windows; 2 = the sign of   */
+/* the log ratio flipped; 3 = walker j's factor dropped.  Never set otherwise.  */
+static int g_exchange_mutation = 0;
+void orc_test_exchange_mutation(int mode) { g_exchange_mutation = mode; }
 
 static int ilog2_exact(int v)
 {
@@ -340,6 +354,13 @@ orc_sim* orc_create(const orc_config* c, const uint8_t* mask, const double* init
     memset(s->swaps, -1, s->S);
     s->ex_prop = calloc(s->h, sizeof(int64_t));
     s->ex_acc = calloc(s->h, sizeof(int64_t));
+    s->rid = malloc(s->S * sizeof(int32_t));
+    s->rt_state = malloc(s->S);
+    s->rt_count = calloc(s->S, sizeof(int32_t));
+    for (int sl = 0; sl < s->S; ++sl) {
+        s->rid[sl] = sl;                           /* replica r starts in slot r */
+        s->rt_state[sl] = (sl / s->m == 0) ? 1 : 0;
+    }
     for (int a = 0; a < s->h; ++a) s->k[a] = c->lnf_k0;
     for (int sl = 0; sl < s->S; ++sl) {
         int a = sl / s->m;
@@ -371,6 +392,7 @@ void orc_destroy(orc_sim* s)
     free(s->lo); free(s->hi); free(s->nreach); free(s->mask); free(s->spins);
     free(s->E); free(s->H); free(s->lng); free(s->flat); free(s->k); free(s->done);
     free(s->swaps); free(s->ex_prop); free(s->ex_acc);
+    free(s->rid); free(s->rt_state); free(s->rt_count);
     free(s);
 }
 
@@ -426,14 +448,16 @@ static int is_flat(const orc_sim* s, int slot)
         sum += v;
         ++n;
     }
+    typedef unsigned __int128 u128;
     if (s->c.flat_rule == 1) {
-        const unsigned __int128 lhs = (unsigned __int128)mn * (unsigned __int128)mn * (unsigned __int128)s->c.flat_den *
-                                      (unsigned __int128)s->c.flat_den;
-        const unsigned __int128 rhs = ((unsigned __int128)s->c.flat_num * (unsigned __int128)s->c.flat_num)
-                                      << s->k[a];
-        return lhs >= rhs;
+        /* min*den < 2^84 here; its square may not fit 128 bits, but num^2 2^k  */
+        /* < 2^81, so min*den >= 2^41 decides the test by itself                */
+        u128 x = (u128)mn * (u128)s->c.flat_den;
+        u128 rhs = ((u128)s->c.flat_num * (u128)s->c.flat_num) << s->k[a];
+        if (x >= ((u128)1 << 41)) return 1;
+        return x * x >= rhs;
     }
-    return (int64_t)s->c.flat_den * mn * n >= (int64_t)s->c.flat_num * sum;
+    return (u128)s->c.flat_den * (u128)mn * (u128)n >= (u128)s->c.flat_num * (u128)sum;
 }
 
 /* Merge (Sec. II.A): the m walkers of a window average their estimators,  */
@@ -492,10 +516,12 @@ static void exchange(orc_sim* s)
                 const double* gj = s->lng + (size_t)j * WB;
                 double delta = (gi[bi - s->lo[a]] - gi[bj - s->lo[a]]) +
                                (gj[bj - s->lo[a + 1]] - gj[bi - s->lo[a + 1]]);
+                if (g_exchange_mutation == 2) delta = -delta;
+                if (g_exchange_mutation == 3) delta = gi[bi - s->lo[a]] - gi[bj - s->lo[a]];
                 uint32_t x[4];
                 draw(s->key, (uint64_t)s->t, (uint32_t)i, TAG_EXCHANGE, x);
                 uint64_t u53 = (((uint64_t)x[3] << 32) | x[2]) >> 11;
-                ok = orc_accept(delta, u53);
+                ok = g_exchange_mutation == 1 ? 1 : orc_accept(delta, u53);
             }
             if (ok) {
                 memcpy(tmp, s->spins + (size_t)i * N, N * sizeof(int16_t));
@@ -505,6 +531,16 @@ static void exchange(orc_sim* s)
                 s->E[i] = s->E[j];
                 s->E[j] = e;
                 s->ex_acc[a] += 1;
+                /* R29: the replica from slot i went up to window a+1, the one  */
+                /* from slot j came down to window a                            */
+                int up = s->rid[i], down = s->rid[j];
+                s->rid[i] = down;
+                s->rid[j] = up;
+                if (a + 1 == h - 1 && s->rt_state[up] == 1) s->rt_state[up] = 2;
+                if (a == 0) {
+                    if (s->rt_state[down] == 2) s->rt_count[down] += 1;
+                    s->rt_state[down] = 1;
+                }
             }
             s->swaps[i] = (int8_t)ok;
             s->swaps[j] = (int8_t)ok;
@@ -592,6 +628,19 @@ void orc_stats(const orc_sim* s, int64_t* attempts, int64_t* ex_prop, int64_t* e
     if (attempts) *attempts = s->attempts;
     if (ex_prop) memcpy(ex_prop, s->ex_prop, s->h * sizeof(int64_t));
     if (ex_acc) memcpy(ex_acc, s->ex_acc, s->h * sizeof(int64_t));
+}
+
+void orc_replicas(const orc_sim* s, int32_t* rid, int32_t* round_trips)
+{
+    if (rid) memcpy(rid, s->rid, s->S * sizeof(int32_t));
+    if (round_trips) memcpy(round_trips, s->rt_count, s->S * sizeof(int32_t));
+}
+
+void orc_set_tables(orc_sim* s, const int64_t* H, const double* lng)
+{
+    size_t SW = (size_t)s->S * s->WB;
+    if (H) memcpy(s->H, H, SW * sizeof(int64_t));
+    if (lng) memcpy(s->lng, lng, SW * sizeof(double));
 }
 
 /* ------------------------------------------------------------------------ */

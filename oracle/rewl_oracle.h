@@ -87,6 +87,17 @@ void     orc_set_window_lng(orc_sim* s, int32_t window, const double* tab);
 /* Counters: attempts made, exchange proposals and acceptances per window pair. */
 void     orc_stats(const orc_sim* s, int64_t* attempts, int64_t* ex_prop, int64_t* ex_acc);
 int      orc_init_attempts_max(const orc_sim* s);         /* longest init drive        */
+/* Replicas (Sec. IV.A, fig:wanderlogs): rid[S] = replica held by each slot
+ * (replica r starts in slot r; it follows its configuration through accepted
+ * exchanges); round_trips[S] by replica = completed visits window 0 -> window
+ * h-1 -> window 0 (starting in window 0 counts as the first visit).  NULL ok.   */
+void     orc_replicas(const orc_sim* s, int32_t* rid, int32_t* round_trips);
+/* Replace every walker's counts H[S*WB] and ln g lng[S*WB] (either may be NULL),
+ * e.g. to start from counts past 2^32.                                          */
+void     orc_set_tables(orc_sim* s, const int64_t* H, const double* lng);
+/* Test hook: plant a mistake in the exchange rule (0 = none, 1 = always accept,
+ * 2 = sign of the log ratio flipped, 3 = walker j's factor dropped).            */
+void     orc_test_exchange_mutation(int mode);
 
 /* --- post-processing (Sec. II.B) ----------------------------------------- */
 /* pieces: h*WB, piece a covers global bins lo[a]..hi[a].  Output: W entries of

@@ -51,19 +51,23 @@ REWL_SWEEP_AUTO, REWL_SWEEP_LANE, REWL_SWEEP_WAVE = 0, 1, 2
 class rewl_tune(ctypes.Structure):
     _fields_ = [("walkers_per_block", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("poll_every", ctypes.c_int32), ("sweep_kind", ctypes.c_int32),
-                ("lds_target_kb", ctypes.c_int32), ("autotune", ctypes.c_int32)]
+                ("lds_target_kb", ctypes.c_int32), ("autotune", ctypes.c_int32),
+                ("guard_band_log2", ctypes.c_int32)]
 
 
 def make_tune(kind="auto", walkers_per_block=0, use_graph=0, poll_every=8, lds_target_kb=0,
-              autotune=0) -> rewl_tune:
+              autotune=0, guard_band_log2=0) -> rewl_tune:
+    """guard_band_log2: 0 keeps the library's 2^-40 guard band of the fast acceptance
+    test; -40..-2 widen it (identical results, more exact slow-path decisions)."""
     return rewl_tune(walkers_per_block, use_graph, poll_every,
-                     {"auto": 0, "lane": 1, "wave": 2}[kind], lds_target_kb, autotune)
+                     {"auto": 0, "lane": 1, "wave": 2}[kind], lds_target_kb, autotune, guard_band_log2)
 
 
 class rewl_stats(ctypes.Structure):
     _fields_ = [("intervals", ctypes.c_int64), ("attempts", ctypes.c_int64),
                 ("windows_done", ctypes.c_int32), ("min_k", ctypes.c_int32),
-                ("sweep_ms", ctypes.c_double), ("interval_ms", ctypes.c_double)]
+                ("sweep_ms", ctypes.c_double), ("interval_ms", ctypes.c_double),
+                ("round_trips", ctypes.c_int64), ("slow_decisions", ctypes.c_int64)]
 
 
 _vp = ctypes.c_void_p
@@ -85,7 +89,7 @@ _sigs = {
     "rewl_thermo": ([ctypes.c_int32, ctypes.c_int32, _vp, ctypes.c_int32, _vp, ctypes.c_int32, _vp, _vp,
                      _vp], ctypes.c_int),
     "rewl_get_state": ([_vp, ctypes.c_int32] + [_vp] * 9, ctypes.c_int),
-    "rewl_get_stats": ([_vp, ctypes.c_int32, _P(rewl_stats), _vp, _vp], ctypes.c_int),
+    "rewl_get_stats": ([_vp, ctypes.c_int32, _P(rewl_stats), _vp, _vp, _vp, _vp], ctypes.c_int),
     "rewl_set_timing": ([_vp, ctypes.c_int32], ctypes.c_int),
     "rewl_checkpoint": ([_vp, _vp, _P(ctypes.c_size_t)], ctypes.c_int),
     "rewl_restore": ([_vp, _vp, ctypes.c_size_t], ctypes.c_int),
@@ -277,13 +281,16 @@ def rewl_get_state(h, instance: int, cfg: rewl_config) -> dict:
     return st
 
 
-def rewl_get_stats(h, instance: int, n_windows: int) -> dict:
+def rewl_get_stats(h, instance: int, n_windows: int, n_slots: int) -> dict:
     s = rewl_stats()
     p = np.zeros(n_windows, np.int64)
     a = np.zeros(n_windows, np.int64)
-    _check(_lib.rewl_get_stats(h, instance, ctypes.byref(s), _p(p), _p(a)), "rewl_get_stats")
+    k = np.zeros(n_windows, np.int32)
+    rt = np.zeros(n_slots, np.int32)
+    _check(_lib.rewl_get_stats(h, instance, ctypes.byref(s), _p(p), _p(a), _p(k), _p(rt)), "rewl_get_stats")
     return dict(intervals=s.intervals, attempts=s.attempts, windows_done=s.windows_done,
-                min_k=s.min_k, sweep_ms=s.sweep_ms, interval_ms=s.interval_ms, ex_prop=p, ex_acc=a)
+                min_k=s.min_k, sweep_ms=s.sweep_ms, interval_ms=s.interval_ms, ex_prop=p, ex_acc=a,
+                k=k, round_trips=rt, round_trips_total=s.round_trips, slow_decisions=s.slow_decisions)
 
 
 def rewl_set_timing(h, on: bool) -> None:
@@ -366,7 +373,8 @@ class Rewl:
         return rewl_get_state(self.h, i, self.cfgs[i])
 
     def stats(self, i: int = 0) -> dict:
-        return rewl_get_stats(self.h, i, self.cfgs[i].n_windows)
+        c = self.cfgs[i]
+        return rewl_get_stats(self.h, i, c.n_windows, c.n_windows * c.walkers_per_window)
 
     def pieces(self, i: int = 0) -> np.ndarray:
         W, WB, lo, hi = self.layouts[i]

@@ -253,7 +253,7 @@ rewl_status sync_flags(rewl_handle* H, bool* all_done)
     for (int i = 0; i < H->n; ++i) {
         const InstCtr& c = H->h_ctr[i];
         if (c.err & kErrInitStuck) return fail(REWL_E_INIT_STUCK, "instance " + std::to_string(i) + ": walker stuck outside its window");
-        if (c.err & kErrOverflow) return fail(REWL_E_OVERFLOW, "instance " + std::to_string(i) + ": histogram count near 2^32");
+        if (c.err & kErrOverflow) return fail(REWL_E_OVERFLOW, "instance " + std::to_string(i) + ": a walker's counts spread over more than 2^32 - X since the last merge");
         if (c.err & kErrExactness) return fail(REWL_E_OVERFLOW, "instance " + std::to_string(i) + ": ln g outside the exact FP64 budget");
         all = all && c.all_done;
     }
@@ -285,7 +285,7 @@ std::vector<Span> spans_of(rewl_handle* H, int i)
     if (d.model == 0) v.push_back({d.lat, (size_t)hi.cfg.L * hi.wpr * S * 8});
     else v.push_back({d.plat, (size_t)hi.N * S});
     v.push_back({d.bin, S * 4});
-    v.push_back({d.H, h * WB * hi.m * 4});
+    v.push_back({d.H, h * WB * hi.m * 8});
     v.push_back({d.base, h * WB * 8});
     v.push_back({d.k, h * 4});
     v.push_back({d.done, h * 4});
@@ -294,6 +294,9 @@ std::vector<Span> spans_of(rewl_handle* H, int i)
     v.push_back({d.ex_prop, h * 8});
     v.push_back({d.ex_acc, h * 8});
     v.push_back({d.merges, h * 4});
+    v.push_back({d.rid, S * 4});
+    v.push_back({d.rt_state, S});
+    v.push_back({d.rt_count, S * 4});
     v.push_back({d.ctr, sizeof(InstCtr)});
     return v;
 }
@@ -449,9 +452,12 @@ static rewl_status create_impl(const rewl_config* cfgs, int32_t n, void* hip_str
     HIP_TRY(hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     if (lds_limit <= 0) lds_limit = 65536;
 
+    if (tune && tune->guard_band_log2 != 0 && (tune->guard_band_log2 < -40 || tune->guard_band_log2 > -2))
+        return fail(REWL_E_INVALID, "guard_band_log2 must be 0 (2^-40) or in [-40, -2]");
     rewl_handle* H = new rewl_handle();
     if (tune) H->tune = *tune;
     if (H->tune.poll_every <= 0) H->tune.poll_every = 8;
+    const double band = H->tune.guard_band_log2 ? std::ldexp(1.0, H->tune.guard_band_log2) : kBand;
     H->n = n;
     H->inst.resize(n);
     std::vector<Inst> devs(n);
@@ -534,6 +540,7 @@ static rewl_status create_impl(const rewl_config* cfgs, int32_t n, void* hip_str
         d.m = hi.m; d.S = hi.S; d.WB = hi.WB; d.log2m = hi.log2m; d.flat_num = c.flat_num;
         d.flat_den = c.flat_den; d.flat_rule = c.flat_rule; d.kfinal = c.lnf_kfinal; d.exch = c.exchange_enabled; d.wpr = hi.wpr;
         d.X = c.exchange_interval; d.k0 = (uint32_t)c.seed; d.k1 = (uint32_t)(c.seed >> 32);
+        d.band = band;
         d.XP = (c.exchange_interval + 31) / 32 * 32;   // two draw chunks of 16
         if ((uint64_t)d.XP * hi.S >= (uint64_t(1) << 32))
             return bail(fail(REWL_E_INVALID, "instance " + std::to_string(i) + ": walkers x interval exceeds 2^32 draws"));
@@ -558,10 +565,18 @@ static rewl_status create_impl(const rewl_config* cfgs, int32_t n, void* hip_str
         if (s == REWL_OK) s = H->alloc(&d.ex_prop, h);
         if (s == REWL_OK) s = H->alloc(&d.ex_acc, h);
         if (s == REWL_OK) s = H->alloc(&d.merges, h);
+        if (s == REWL_OK) s = H->alloc(&d.rid, S);
+        if (s == REWL_OK) s = H->alloc(&d.rt_state, S);
+        if (s == REWL_OK) s = H->alloc(&d.rt_count, S);
         if (s != REWL_OK) return bail(s);
 
         std::vector<int32_t> kinit(h, c.lnf_k0), zeros(h, 0);
-        std::vector<int32_t> merges0(h, -1);
+        std::vector<int32_t> merges0(h, -1), rid0(S);
+        std::vector<int8_t> rts0(S);
+        for (size_t sl = 0; sl < S; ++sl) {
+            rid0[sl] = (int32_t)sl;                            // replica r starts in slot r
+            rts0[sl] = sl / hi.m == 0 ? 1 : 0;                 // starting in window 0 counts as a visit
+        }
         hipStream_t st = H->stream;
         bool ok = true;
         ok &= hipMemcpyAsync(d.lo, hi.lo.data(), h * 4, hipMemcpyHostToDevice, st) == hipSuccess;
@@ -570,8 +585,11 @@ static rewl_status create_impl(const rewl_config* cfgs, int32_t n, void* hip_str
         ok &= hipMemcpyAsync(d.mask, hi.mask.data(), hi.W, hipMemcpyHostToDevice, st) == hipSuccess;
         ok &= hipMemcpyAsync(d.k, kinit.data(), h * 4, hipMemcpyHostToDevice, st) == hipSuccess;
         ok &= hipMemcpyAsync(d.merges, merges0.data(), h * 4, hipMemcpyHostToDevice, st) == hipSuccess;
+        ok &= hipMemcpyAsync(d.rid, rid0.data(), S * 4, hipMemcpyHostToDevice, st) == hipSuccess;
+        ok &= hipMemcpyAsync(d.rt_state, rts0.data(), S, hipMemcpyHostToDevice, st) == hipSuccess;
+        ok &= hipMemsetAsync(d.rt_count, 0, S * 4, st) == hipSuccess;
         ok &= hipMemsetAsync(d.done, 0, h * 4, st) == hipSuccess;
-        ok &= hipMemsetAsync(d.H, 0, h * WB * hi.m * 4, st) == hipSuccess;
+        ok &= hipMemsetAsync(d.H, 0, h * WB * hi.m * 8, st) == hipSuccess;
         ok &= hipMemsetAsync(d.base, 0, h * WB * 8, st) == hipSuccess;
         ok &= hipMemsetAsync(d.flat, 0, S, st) == hipSuccess;
         ok &= hipMemsetAsync(d.swaps, 0xff, S, st) == hipSuccess;
@@ -809,12 +827,12 @@ rewl_status rewl_get_state(rewl_handle* H, int32_t i, uint8_t* spins, int32_t* b
     std::vector<int32_t> kk(h), dd(h);
     HIP_TRY(hipMemcpyAsync(kk.data(), d.k, h * 4, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipMemcpyAsync(dd.data(), d.done, h * 4, hipMemcpyDeviceToHost, st));
-    std::vector<uint32_t> Hd;
+    std::vector<uint64_t> Hd;
     std::vector<double> base;
     if (Hout || lng) {
         Hd.resize(h * WB * m);
         base.resize(h * WB);
-        HIP_TRY(hipMemcpyAsync(Hd.data(), d.H, Hd.size() * 4, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(Hd.data(), d.H, Hd.size() * 8, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipMemcpyAsync(base.data(), d.base, base.size() * 8, hipMemcpyDeviceToHost, st));
     }
     std::vector<uint64_t> lat;
@@ -855,8 +873,8 @@ rewl_status rewl_get_state(rewl_handle* H, int32_t i, uint8_t* spins, int32_t* b
             const size_t a = sl / m;
             const double scale = std::ldexp(1.0, -kk[a]);
             for (size_t b = 0; b < WB; ++b) {
-                const uint32_t hv = Hd[sl * WB + b];
-                if (Hout) Hout[sl * WB + b] = hv;
+                const uint64_t hv = Hd[sl * WB + b];
+                if (Hout) Hout[sl * WB + b] = (int64_t)hv;
                 if (lng) lng[sl * WB + b] = std::fma((double)hv, scale, base[a * WB + b]);
             }
         }
@@ -864,17 +882,21 @@ rewl_status rewl_get_state(rewl_handle* H, int32_t i, uint8_t* spins, int32_t* b
     return REWL_OK;
 }
 
-rewl_status rewl_get_stats(rewl_handle* H, int32_t i, rewl_stats* out, int64_t* ex_prop, int64_t* ex_acc)
+rewl_status rewl_get_stats(rewl_handle* H, int32_t i, rewl_stats* out, int64_t* ex_prop, int64_t* ex_acc,
+                           int32_t* k, int32_t* round_trips)
 {
     rewl_status s = check_inst(H, i);
     if (s != REWL_OK) return s;
     HostInst& hi = H->inst[i];
-    std::vector<int32_t> kk(hi.h);
+    std::vector<int32_t> kk(hi.h), rt(hi.S);
     HIP_TRY(hipMemcpyAsync(kk.data(), hi.dev.k, hi.h * 4, hipMemcpyDeviceToHost, H->stream));
+    HIP_TRY(hipMemcpyAsync(rt.data(), hi.dev.rt_count, (size_t)hi.S * 4, hipMemcpyDeviceToHost, H->stream));
     if (ex_prop) HIP_TRY(hipMemcpyAsync(ex_prop, hi.dev.ex_prop, hi.h * 8, hipMemcpyDeviceToHost, H->stream));
     if (ex_acc) HIP_TRY(hipMemcpyAsync(ex_acc, hi.dev.ex_acc, hi.h * 8, hipMemcpyDeviceToHost, H->stream));
     HIP_TRY(hipMemcpyAsync(H->h_ctr, H->d_ctr, sizeof(InstCtr) * H->n, hipMemcpyDeviceToHost, H->stream));
     HIP_TRY(hipStreamSynchronize(H->stream));
+    if (k) std::copy(kk.begin(), kk.end(), k);
+    if (round_trips) std::copy(rt.begin(), rt.end(), round_trips);
     if (out) {
         const InstCtr& c = H->h_ctr[i];
         out->intervals = c.t;
@@ -883,6 +905,10 @@ rewl_status rewl_get_stats(rewl_handle* H, int32_t i, rewl_stats* out, int64_t* 
         out->min_k = *std::min_element(kk.begin(), kk.end());
         out->sweep_ms = H->sweep_ms;
         out->interval_ms = H->interval_ms;
+        int64_t tot = 0;
+        for (int32_t v : rt) tot += v;
+        out->round_trips = tot;
+        out->slow_decisions = c.slow;
     }
     return REWL_OK;
 }
@@ -1020,7 +1046,7 @@ rewl_status rewl_checkpoint(rewl_handle* H, void* buf, size_t* len)
     }
     if (*len < total) return fail(REWL_E_INVALID, "checkpoint buffer too small");
     char* p = (char*)buf;
-    const uint64_t magic = 0x4c57455231ull, count = (uint64_t)H->n;
+    const uint64_t magic = 0x4c57455232ull, count = (uint64_t)H->n;
     std::memcpy(p, &magic, 8);
     std::memcpy(p + 8, &count, 8);
     p += 16;
@@ -1044,7 +1070,7 @@ rewl_status rewl_restore(rewl_handle* H, const void* buf, size_t len)
     if (len != total) return fail(REWL_E_INVALID, "checkpoint size does not match this handle");
     std::memcpy(&magic, buf, 8);
     std::memcpy(&count, (const char*)buf + 8, 8);
-    if (magic != 0x4c57455231ull || count != (uint64_t)H->n) return fail(REWL_E_INVALID, "not a checkpoint of this batch");
+    if (magic != 0x4c57455232ull || count != (uint64_t)H->n) return fail(REWL_E_INVALID, "not a checkpoint of this batch");
     const char* p = (const char*)buf + 16;
     for (int i = 0; i < H->n; ++i)
         for (const Span& sp : spans_of(H, i)) {

@@ -139,28 +139,24 @@ __device__ inline bool accept_slow(double delta, uint64_t u53)
 }
 
 // Guard band of the fast comparison: the device log is within a few ulp
-// (|log u| <= 36.8, ulp <= 7.2e-15); 2^-40 leaves a margin above 100 ulp.
+// (|log u| <= 36.8, ulp <= 7.2e-15); 2^-40 leaves a margin above 100 ulp.  A
+// handle may widen it (every decision stays exact: only more of them go to the
+// slow path), which is how the slow path is exercised under test.
 constexpr double kBand = 0x1p-40;
 
 // Threshold of the fast test for a draw u53: vb = log(u53 2^-53) + band, or
 // -DBL_MAX for u53 = 0 (every finite delta accepts, an out-of-window move with
 // delta = -inf does not).  accept  <=>  delta > log(u53 2^-53)  exactly; the
 // fast test decides whenever delta is outside [vb - 2 band, vb].
-__device__ __forceinline__ double threshold_of(uint64_t u53)
+__device__ __forceinline__ double threshold_of(uint64_t u53, double band)
 {
-    return u53 == 0 ? -0x1.fffffffffffffp+1023 : log(__builtin_ldexp((double)u53, -53)) + kBand;
+    return u53 == 0 ? -0x1.fffffffffffffp+1023 : log(__builtin_ldexp((double)u53, -53)) + band;
 }
 
 // 1 accept, 0 reject, 2 undecided (decide with accept_slow).
-__device__ __forceinline__ int decide_fast(double delta, double vb)
+__device__ __forceinline__ int decide_fast(double delta, double vb, double band)
 {
-    return delta > vb ? 1 : (delta >= vb - 2.0 * kBand ? 2 : 0);
-}
-
-__device__ inline bool accept_full(double delta, uint64_t u53)
-{
-    const int f = decide_fast(delta, threshold_of(u53));
-    return f == 2 ? accept_slow(delta, u53) : (f == 1);
+    return delta > vb ? 1 : (delta >= vb - 2.0 * band ? 2 : 0);
 }
 
 // ---------------------------------------------------------- descriptors
@@ -169,6 +165,7 @@ enum : int32_t { kErrOverflow = 1, kErrInitStuck = 2, kErrExactness = 4 };
 // Device counters of one instance (one cache line each would be overkill).
 struct InstCtr {
     int64_t t;          // completed intervals
+    int64_t slow;       // acceptance decisions taken by the exact slow path
     int32_t all_done;   // every window converged
     int32_t stopped;    // the interval that finished the run has been counted
     int32_t n_done;     // converged windows
@@ -188,7 +185,8 @@ struct Inst {
     uint64_t* lat;      // Ising: [S][L*wpr] words, bit x of row y's word = spin up
     uint8_t* plat;      // Potts: [S][N] bytes
     int32_t* bin;       // [S]   global energy bin of the slot's configuration
-    uint32_t* H;        // [S][WB] (slot = a*m + r): walker-major
+    uint64_t* H;        // [S][WB] (slot = a*m + r): walker-major counts since the
+                        //         window's last merge
     double* base;       // [h][WB] window ln g base: ln g_w = base + 2^-k H_w
     int32_t* lo;        // [h]
     int32_t* hi;        // [h]
@@ -204,22 +202,37 @@ struct Inst {
     int64_t* ex_prop;   // [h]
     int64_t* ex_acc;    // [h]
     int32_t* merges;    // [h] interval of each window's last merge
+    int32_t* rid;       // [S] replica (configuration) held by each slot
+    int8_t* rt_state;   // [S] per replica: 0 not yet in window 0, 1 in or last at
+                        //     window 0, 2 reached window h-1 since
+    int32_t* rt_count;  // [S] per replica: completed round trips 0 -> h-1 -> 0
+    double band;        // guard band of the fast acceptance test
     InstCtr* ctr;
 };
 
 // Flatness of one walker from the minimum and sum of its counts over the n
 // levels of its window that occur.  Rule 0 (Sec. II.A): min >= num/den of the
-// mean.  Rule 1 (Eq. (8)): min >= (num/den) / sqrt(ln f), ln f = 2^-k, decided
-// exactly as min^2 den^2 >= num^2 2^k (both below 2^105).
-__device__ __forceinline__ bool walker_flat(const Inst& I, uint32_t mn, uint64_t sum, int64_t n, int k)
+// mean, decided as den min n >= num sum.  Rule 1 (Eq. (8)): min >= (num/den) /
+// sqrt(ln f), ln f = 2^-k, decided as (min den)^2 >= num^2 2^k.  Both exactly
+// in 128-bit integers (num, den <= 2^31, n <= 2^17, k <= 40).
+__device__ __forceinline__ bool walker_flat(const Inst& I, uint64_t mn, uint64_t sum, int64_t n, int k)
 {
+    typedef unsigned __int128 u128;
     if (I.flat_rule == 1) {
-        const unsigned __int128 lhs = (unsigned __int128)((uint64_t)mn * mn) *
-                                      (uint64_t)((int64_t)I.flat_den * I.flat_den);
-        const unsigned __int128 rhs = (unsigned __int128)((uint64_t)((int64_t)I.flat_num * I.flat_num)) << k;
-        return lhs >= rhs;
+        const u128 x = (u128)mn * (uint64_t)I.flat_den;                 // < 2^84
+        const u128 rhs = (u128)((uint64_t)I.flat_num * (uint64_t)I.flat_num) << k;  // < 2^81
+        if (x >= ((u128)1 << 41)) return true;                          // x^2 >= 2^82 > rhs
+        return x * x >= rhs;
     }
-    return (int64_t)I.flat_den * (int64_t)mn * n >= (int64_t)I.flat_num * (int64_t)sum;
+    return (u128)mn * (uint64_t)I.flat_den * (uint64_t)n >= (u128)sum * (uint64_t)I.flat_num;
+}
+
+// 64-bit lane exchange through two 32-bit shuffles.
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int mask)
+{
+    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, mask);
+    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), mask);
+    return ((uint64_t)hi << 32) | lo;
 }
 
 // A sweep tile: nw consecutive walkers of one window of one instance.

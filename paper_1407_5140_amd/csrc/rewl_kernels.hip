@@ -55,7 +55,7 @@ __global__ void __launch_bounds__(256) k_rng(const Inst* __restrict__ insts,
         }
         const size_t idx = (size_t)slot * XP + j;
         I.rpack[idx] = pack;
-        I.rv[idx] = threshold_of(u53_of(x));
+        I.rv[idx] = threshold_of(u53_of(x), I.band);
     }
 }
 
@@ -94,6 +94,20 @@ __device__ __forceinline__ T gload(const T* p)
     return *(const __attribute__((address_space(1))) T*)p;
 }
 
+// Lane l's value of a wave-uniform lane index l (v_readlane).
+__device__ __forceinline__ uint32_t rl(uint32_t v, int l)
+{
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
+}
+__device__ __forceinline__ uint64_t rl64(uint64_t v, int l)
+{
+    return ((uint64_t)rl((uint32_t)(v >> 32), l) << 32) | rl((uint32_t)v, l);
+}
+__device__ __forceinline__ double rld(double v, int l)
+{
+    return __builtin_bit_cast(double, rl64(__builtin_bit_cast(uint64_t, v), l));
+}
+
 template <int MODEL, int WPR>
 __device__ void sweep_tile(const Inst& I, const Tile& tile, char* smem)
 {
@@ -108,9 +122,14 @@ __device__ void sweep_tile(const Inst& I, const Tile& tile, char* smem)
     const int nthr = blockDim.x;
     const int lnw = __builtin_ctz(nw);                           // nw is a power of two
 
-    // ---- stage the window table, the tile's histograms and lattices in LDS;
-    //      levels that never occur carry the sentinel 0xffffffff (never visited,
-    //      excluded from the flatness minimum, written back as 0)
+    // ---- stage the window table, the tile's histograms and lattices in LDS.
+    //      A walker's counts enter LDS relative to its own smallest count over
+    //      the levels of the window that occur (cw, kept by lane l for walker l):
+    //      every decision of the sweep compares two ln g values of one walker,
+    //      so a per-walker constant cancels, and the 32-bit LDS entries only
+    //      need to hold the spread of the counts, not their size.  Levels that
+    //      never occur carry the sentinel 0xffffffff (never visited, excluded
+    //      from the flatness minimum, written back as 0).
     // bins b >= width (a window narrower than WB) are outside the window: +inf
     // table (moves there are rejected) and the never-visited sentinel
     const int width = I.hi[a] - lo + 1;
@@ -118,15 +137,36 @@ __device__ void sweep_tile(const Inst& I, const Tile& tile, char* smem)
         const int b = i - kPad;
         lbase[i] = (b >= 0 && b < width) ? I.base[(size_t)a * WB + b] : __builtin_inf();
     }
+    uint64_t cw = 0;
+    for (int l = 0; l < nw; ++l) {
+        uint64_t mn = ~0ull, mx = 0;
+        for (int b = lane; b < width; b += nthr)
+            if (I.mask[lo + b]) {
+                const uint64_t v = I.H[(size_t)(slot0 + l) * WB + b];
+                mn = v < mn ? v : mn;
+                mx = v > mx ? v : mx;
+            }
+        for (int off = 32; off > 0; off >>= 1) {
+            const uint64_t m2 = shfl_xor_u64(mn, off), x2 = shfl_xor_u64(mx, off);
+            mn = m2 < mn ? m2 : mn;
+            mx = x2 > mx ? x2 : mx;
+        }
+        if (lane == l) cw = mn;
+        // the spread plus this interval's X updates must stay below the sentinel
+        if (lane == 0 && mx - mn >= 0xffffffffull - (uint64_t)I.X) atomicOr(&I.ctr->err, kErrOverflow);
+    }
     // global H is walker-major: H[slot][bin]; consecutive threads take consecutive bins
-    for (int l = 0; l < nw; ++l)
+    for (int l = 0; l < nw; ++l) {
+        const uint64_t cl = rl64(cw, l);
         for (int i = lane; i < nbins; i += nthr) {
             const int b = i - kPad;
             uint32_t hv = 0;
             if (b >= 0 && b < WB)
-                hv = (b < width && I.mask[lo + b]) ? I.H[(size_t)(slot0 + l) * WB + b] : 0xffffffffu;
+                hv = (b < width && I.mask[lo + b]) ? (uint32_t)(I.H[(size_t)(slot0 + l) * WB + b] - cl)
+                                                    : 0xffffffffu;
             lH[(i << lnw) + l] = hv;
         }
+    }
     // lattices are walker-major too: lat[slot][word] / plat[slot][site]
     if (MODEL == 0) {
         uint64_t* lat = (uint64_t*)latp;
@@ -152,6 +192,7 @@ __device__ void sweep_tile(const Inst& I, const Tile& tile, char* smem)
         uint32_t hc = lH[(b << lnw) + lane];
         double lngc = __builtin_fma((double)hc, scale, lbase[b]);
         const double incv = inc ? scale : 0.0;
+        const double band2 = 2.0 * I.band;
 
         // one flip attempt with the precomputed draw (pk, vb) of attempt j;
         // lH always holds the walker's current counts, including bin b
@@ -215,9 +256,12 @@ __device__ void sweep_tile(const Inst& I, const Tile& tile, char* smem)
             const double delta = lngc - lngn;                    // exact (or -inf)
             // delta > vb accepts for certain; below vb - 2 band rejects for certain
             bool f = delta > vb;
-            const bool band = !f && delta >= vb - 2.0 * kBand;
+            const bool band = !f && delta >= vb - band2;
             if (__builtin_expect(__any(band), 0)) {
-                if (band) f = slow_decide(I, T0 + (uint64_t)j, (uint32_t)slot, delta);
+                if (band) {
+                    f = slow_decide(I, T0 + (uint64_t)j, (uint32_t)slot, delta);
+                    atomicAdd((unsigned long long*)&I.ctr->slow, 1ull);
+                }
             }
             if (f) {
                 if (MODEL == 0) ((uint64_t*)latp)[waddr] = wnew;
@@ -271,12 +315,14 @@ __device__ void sweep_tile(const Inst& I, const Tile& tile, char* smem)
     }
     __syncthreads();
 
-    // ---- write back
-    for (int l = 0; l < nw; ++l)
+    // ---- write back (absolute counts: the walker's offset added back)
+    for (int l = 0; l < nw; ++l) {
+        const uint64_t cl = rl64(cw, l);
         for (int bb = lane; bb < WB; bb += nthr) {
             const uint32_t hv = lH[((bb + kPad) << lnw) + l];
-            I.H[(size_t)(slot0 + l) * WB + bb] = hv == 0xffffffffu ? 0u : hv;
+            I.H[(size_t)(slot0 + l) * WB + bb] = hv == 0xffffffffu ? 0ull : (uint64_t)hv + cl;
         }
+    }
     if (MODEL == 0) {
         const uint64_t* lat = (const uint64_t*)latp;
         const int nwords = L * WPR;
@@ -299,8 +345,8 @@ __device__ void sweep_tile(const Inst& I, const Tile& tile, char* smem)
             sum += v == 0xffffffffu ? 0u : v;
         }
         const int slot = slot0 + lane;
-        if (walker_flat(I, mn, sum, I.nreach[a], k)) I.flat[slot] = 1;
-        if (sum + (uint64_t)X >= 0xffffffffull) atomicOr(&I.ctr->err, kErrOverflow);
+        const int64_t n = I.nreach[a];
+        if (walker_flat(I, (uint64_t)mn + cw, sum + (uint64_t)n * cw, n, k)) I.flat[slot] = 1;
     }
 }
 
@@ -344,18 +390,6 @@ __host__ __device__ inline size_t wave_lds_bytes(int model, int L, int WB, int G
     return s;
 }
 
-__device__ __forceinline__ uint32_t rl(uint32_t v, int l)
-{
-    return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
-}
-__device__ __forceinline__ uint64_t rl64(uint64_t v, int l)
-{
-    return ((uint64_t)rl((uint32_t)(v >> 32), l) << 32) | rl((uint32_t)v, l);
-}
-__device__ __forceinline__ double rld(double v, int l)
-{
-    return __builtin_bit_cast(double, rl64(__builtin_bit_cast(uint64_t, v), l));
-}
 __device__ __forceinline__ uint32_t shfl32(uint32_t v, int src)
 {
     return (uint32_t)__builtin_amdgcn_ds_bpermute(src << 2, (int)v);
@@ -427,12 +461,29 @@ __device__ void sweep_wave(const Inst& I, const Tile& tile, char* smem)
     uint64_t* lrow = (uint64_t*)(smem + off_map + (size_t)G * M * 8) + (size_t)wave * L * wpr;
     // site -> map entry: the site itself when every site has one, else site mod 4096
     auto ent = [&](int site) { return WIDE ? (site & (kWaveMapMax - 1)) : site; };
+    // the walker's counts relative to its smallest over the occurring levels
+    // (a per-walker constant cancels from every decision), see sweep_tile
+    uint64_t cw = 0;
     if (active) {
+        uint64_t mn = ~0ull, mx = 0;
+        for (int b = lane; b < width; b += 64)
+            if (I.mask[lo + b]) {
+                const uint64_t v = I.H[(size_t)slot * WB + b];
+                mn = v < mn ? v : mn;
+                mx = v > mx ? v : mx;
+            }
+        for (int off = 32; off > 0; off >>= 1) {
+            const uint64_t m2 = shfl_xor_u64(mn, off), x2 = shfl_xor_u64(mx, off);
+            mn = m2 < mn ? m2 : mn;
+            mx = x2 > mx ? x2 : mx;
+        }
+        cw = mn;
+        if (lane == 0 && mx - mn >= 0xffffffffull - (uint64_t)I.X) atomicOr(&I.ctr->err, kErrOverflow);
         for (int i = lane; i < nbins; i += 64) {
             const int b = i - kPad;
             uint32_t hv = 0;
             if (b >= 0 && b < WB)
-                hv = (b < width && I.mask[lo + b]) ? I.H[(size_t)slot * WB + b] : 0xffffffffu;
+                hv = (b < width && I.mask[lo + b]) ? (uint32_t)(I.H[(size_t)slot * WB + b] - cw) : 0xffffffffu;
             lH[i] = hv;
         }
         for (int i = lane; i < M; i += 64) lmap[i] = 0;
@@ -452,6 +503,7 @@ __device__ void sweep_wave(const Inst& I, const Tile& tile, char* smem)
     const int64_t X = I.X;
     const uint64_t T0 = (uint64_t)I.ctr->t * (uint64_t)X;
     const uint32_t q = (uint32_t)I.q, qm1 = q - 1;
+    const double band = I.band;
     const int b = __builtin_amdgcn_readfirstlane(I.bin[slot] - lo + kPad);
 
     // register window of the walker's table: lane l holds ln g of bin b0 + l
@@ -503,8 +555,8 @@ __device__ void sweep_wave(const Inst& I, const Tile& tile, char* smem)
             }
         };
         evaluate();
-        const double vbl = threshold_of(u53_of(x));
-        const double vbl2 = vbl - 2.0 * kBand;    // below it a reject is certain
+        const double vbl = threshold_of(u53_of(x), band);
+        const double vbl2 = vbl - 2.0 * band;     // below it a reject is certain
         // earlier attempts of the chunk whose site lies in this attempt's neighbourhood
         if (lane < n) atomicOr((unsigned long long*)&lmap[ent(site)], 1ull << lane);
         const uint64_t pm = (lmap[ent(site)] | lmap[ent(s_up)] | lmap[ent(s_dn)] | lmap[ent(s_lf)] |
@@ -543,6 +595,7 @@ __device__ void sweep_wave(const Inst& I, const Tile& tile, char* smem)
             while (__builtin_expect((amb & below) != 0, 0)) {
                 const int kk = (int)__builtin_ctzll(amb);
                 amb &= amb - 1;
+                if (lane == 0) atomicAdd((unsigned long long*)&I.ctr->slow, 1ull);
                 if (__builtin_amdgcn_readfirstlane(
                         slow_decide(I, T0 + (uint64_t)j0 + (uint64_t)kk, (uint32_t)slot, rld(dl, kk)) ? 1 : 0)) {
                     js = kk;
@@ -591,7 +644,7 @@ __device__ void sweep_wave(const Inst& I, const Tile& tile, char* smem)
     // ---- write back
     for (int i = lane; i < WB; i += 64) {
         const uint32_t hv = lH[i + kPad];
-        I.H[(size_t)slot * WB + i] = hv == 0xffffffffu ? 0u : hv;
+        I.H[(size_t)slot * WB + i] = hv == 0xffffffffu ? 0ull : (uint64_t)hv + cw;
     }
     if (MODEL == 0) {
         for (int i = lane; i < L * wpr; i += 64) I.lat[(size_t)slot * L * wpr + i] = lrow[i];
@@ -624,8 +677,8 @@ __device__ void sweep_wave(const Inst& I, const Tile& tile, char* smem)
         }
         if (lane == 0) {
             const uint64_t tot = ((uint64_t)shi << 32) | slo;
-            if (walker_flat(I, mn, tot, I.nreach[a], k)) I.flat[slot] = 1;
-            if (tot + (uint64_t)X >= 0xffffffffull) atomicOr(&I.ctr->err, kErrOverflow);
+            const int64_t n = I.nreach[a];
+            if (walker_flat(I, (uint64_t)mn + cw, tot + (uint64_t)n * cw, n, k)) I.flat[slot] = 1;
         }
     }
 }
@@ -669,11 +722,13 @@ __global__ void __launch_bounds__(256) k_merge(const Inst* __restrict__ insts,
     const int WB = I.WB, m = I.m, k = I.k[a], lo = I.lo[a];
     const int sh = k + I.log2m;
     double* base = I.base + (size_t)a * WB;
-    uint32_t* H = I.H + (size_t)a * m * WB;                    // the window's walkers, H[r][bin]
+    uint64_t* H = I.H + (size_t)a * m * WB;                    // the window's walkers, H[r][bin]
     double mn = __builtin_inf(), mx = 0.0;
+    bool big = false;
     for (int b = tid; b < WB; b += blockDim.x) {
         uint64_t s = 0;
         for (int r = 0; r < m; ++r) s += H[(size_t)r * WB + b];
+        big |= s >= (1ull << 53);                             // (double)s would round
         const double nb = base[b] + __builtin_ldexp((double)s, -sh);
         base[b] = nb;
         if (b <= I.hi[a] - lo && I.mask[lo + b]) mn = nb < mn ? nb : mn;
@@ -696,8 +751,9 @@ __global__ void __launch_bounds__(256) k_merge(const Inst* __restrict__ insts,
     // values are multiples of 2^-sh, or of 2^-20 after a warm start: exact below 2^(52 - that)
     if (tid == 0) okflag = red[0] < __builtin_ldexp(1.0, 52 - (sh > 20 ? sh : 20));
     __syncthreads();
+    if (__syncthreads_or(big) && tid == 0) okflag = 0;
     for (int b = tid; b < WB; b += blockDim.x) base[b] = base[b] - shift;
-    for (size_t i = tid; i < (size_t)WB * m; i += blockDim.x) H[i] = 0u;
+    for (size_t i = tid; i < (size_t)WB * m; i += blockDim.x) H[i] = 0ull;
     for (int r = tid; r < m; r += blockDim.x) I.flat[a * m + r] = 0;
     if (tid == 0) {
         if (!okflag) atomicOr(&I.ctr->err, kErrExactness);
@@ -750,12 +806,19 @@ __global__ void __launch_bounds__(256) k_exchange(const Inst* __restrict__ insts
         const double sb = __builtin_ldexp(1.0, -I.k[a + 1]);
         const double* ba = I.base + (size_t)a * WB;
         const double* bb = I.base + (size_t)(a + 1) * WB;
-        const uint32_t* Hi = I.H + (size_t)i * WB;
-        const uint32_t* Hj = I.H + (size_t)j * WB;
+        const uint64_t* Hi = I.H + (size_t)i * WB;
+        const uint64_t* Hj = I.H + (size_t)j * WB;
         auto gi = [&](int bin) { return __builtin_fma((double)Hi[bin - loa], sa, ba[bin - loa]); };
         auto gj = [&](int bin) { return __builtin_fma((double)Hj[bin - lob], sb, bb[bin - lob]); };
         const double delta = (gi(bi) - gi(bj)) + (gj(bj) - gj(bi));
-        acc = accept_full(delta, u53_of(draw(I.k0, I.k1, (uint64_t)t, (uint32_t)i, kTagExchange)));
+        const uint64_t u53 = u53_of(draw(I.k0, I.k1, (uint64_t)t, (uint32_t)i, kTagExchange));
+        const int f = decide_fast(delta, threshold_of(u53, I.band), I.band);
+        if (f == 2) {
+            acc = accept_slow(delta, u53);
+            if (lane == 0) atomicAdd((unsigned long long*)&I.ctr->slow, 1ull);
+        } else {
+            acc = f == 1;
+        }
     }
     if (acc) {
         if (I.model == 0) {
@@ -791,6 +854,17 @@ __global__ void __launch_bounds__(256) k_exchange(const Inst* __restrict__ insts
         if (acc) {
             I.bin[i] = bj;
             I.bin[j] = bi;
+            // replicas follow their configurations; a round trip is window 0,
+            // then window h-1, then window 0 again (each replica takes part in
+            // one proposal per interval, so these updates do not race)
+            const int up = I.rid[i], down = I.rid[j];      // up: window a -> a+1
+            I.rid[i] = down;
+            I.rid[j] = up;
+            if (a + 1 == I.h - 1 && I.rt_state[up] == 1) I.rt_state[up] = 2;
+            if (a == 0) {
+                if (I.rt_state[down] == 2) I.rt_count[down] += 1;
+                I.rt_state[down] = 1;
+            }
             atomicAdd((unsigned long long*)&I.ex_acc[a], 1ull);
         }
         atomicAdd((unsigned long long*)&I.ex_prop[a], 1ull);
@@ -1034,7 +1108,7 @@ __global__ void k_accept_probe(const double* __restrict__ delta, const uint64_t*
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) {
-        const int f = decide_fast(delta[i], threshold_of(u53[i]));
+        const int f = decide_fast(delta[i], threshold_of(u53[i], kBand), kBand);
         out[i] = f == 2 ? (accept_slow(delta[i], u53[i]) ? 3 : 2) : f;
     }
 }

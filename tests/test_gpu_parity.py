@@ -143,6 +143,8 @@ def test_ising_L8_full_run_bitwise(rw):
     st = gpu.stats()
     ost = orc.stats()
     assert np.array_equal(st["ex_prop"], ost["ex_prop"]) and np.array_equal(st["ex_acc"], ost["ex_acc"])
+    assert np.array_equal(st["round_trips"], orc.replicas()["round_trips"])
+    assert st["round_trips_total"] > 0
 
 
 @pytest.mark.parametrize("kw", [
@@ -254,3 +256,168 @@ def test_batch64_first_interval_autotuned(rw):
     for i, o in enumerate(orcs):
         o.run(1)
         assert_same(g.state(i), o.state(), f"batch instance {i} after 1 interval")
+
+
+# ------------------------------------------- the exact slow path under lockstep
+WIDE_BAND = [SMALL[1], SMALL[2], SMALL[3], SMALL[5], SMALL[6], SMALL[10], SMALL[12]]
+
+
+@pytest.mark.parametrize("kind", ["lane", "wave"])
+@pytest.mark.parametrize("kw", WIDE_BAND, ids=lambda kw: f"{kw['model']}-L{kw['L']}-m{kw['m']}-seed{kw['seed']}")
+def test_lockstep_wide_guard_band(rw, kw, kind):
+    """Guard band widened from 2^-40 to 2^-6: hundreds to thousands of decisions per run
+    fall inside it and are taken by the double-double slow path (the lane sweep's per-lane branch,
+    the wave sweep's in-order re-decision loop, the exchange); every decision is exact,
+    so the run must stay bit-identical to the oracle."""
+    tune = rw.make_tune(kind, 0, 0, 8, guard_band_log2=-6)
+    gpu, _, _ = _lockstep(rw, kw, 25, tune=tune, every=5)
+    assert gpu.info()["sweep_kind"] == kind
+    assert gpu.stats()["slow_decisions"] > 500
+
+
+def test_default_guard_band_rarely_used(rw):
+    """At the default 2^-40 band the slow path is ~1e-12 per attempt: none in a short run."""
+    kw = SMALL[2]
+    g = rw.Rewl([rw.make_config(**kw)])
+    g.run(20)
+    assert g.stats()["slow_decisions"] == 0
+
+
+# ------------------------------------- full-size merges, done and frozen windows
+@pytest.mark.parametrize("kw", [
+    dict(model="ising", L=64, n_windows=16, m=64, kfinal=10, X=10000, seed=1, flat_rule="visits", flat=(0, 1)),
+    dict(model="potts", q=10, L=32, n_windows=32, m=128, kfinal=10, X=10000, seed=1, flat_rule="visits",
+         flat=(0, 1)),
+], ids=["ising-L64-h16-m64", "potts-q10-L32-h32-m128"])
+@pytest.mark.parametrize("kind", ["auto", "lane"])
+def test_full_size_merges_to_done(rw, kw, kind):
+    """The full-size workloads with Eq. (8) at a = 0: every walker passes at every
+    interval, so all windows merge (m = 64 / 128 walkers of 864 / 236 bins) at every
+    interval until ln f reaches 2^-10 and the run stops, bit-exact throughout."""
+    gpu, orc, done = _lockstep(rw, kw, 12, tune=_tune(rw, kind))
+    assert done and orc.t == 10
+    assert list(gpu.stats()["k"]) == [10] * kw["n_windows"]
+
+
+@pytest.mark.parametrize("kw", [
+    dict(model="ising", L=16, n_windows=4, m=64, kfinal=7, X=2000, seed=3),
+    dict(model="potts", q=4, L=8, n_windows=3, m=128, kfinal=5, X=1000, seed=5),
+], ids=["ising-L16-m64", "potts-q4-L8-m128"])
+@pytest.mark.parametrize("kind", ["lane", "wave"])
+def test_staggered_convergence_with_frozen_windows(rw, kw, kind):
+    """m = 64 / 128 walkers per window run to the end under the 80 % rule; windows
+    converge hundreds of intervals apart, so converged windows walk frozen and keep
+    exchanging while the others merge.  Bit-exact to the oracle, including the
+    exchange counters and every replica's round trips."""
+    gpu, orc, done = _lockstep(rw, kw, 5000, tune=_tune(rw, kind, poll=50), every=50)
+    assert done
+    st, ost = gpu.stats(), orc.stats()
+    assert np.array_equal(st["ex_prop"], ost["ex_prop"]) and np.array_equal(st["ex_acc"], ost["ex_acc"])
+    rt = orc.replicas()["round_trips"]
+    assert np.array_equal(st["round_trips"], rt) and rt.sum() > 100
+    assert st["round_trips_total"] == rt.sum()
+
+
+# ----------------------------------------------------------- batch graph replay
+@pytest.mark.parametrize("kind", ["lane", "wave"])
+def test_batch_graph_replay_mixed(rw, kind):
+    """A mixed batch replays its captured interval graph for 60 intervals, with host
+    syncs, state reads and eager oracle work between replays; every replay's result
+    is compared with the oracle."""
+    kws = [dict(model="ising", L=16, n_windows=4, m=8, kfinal=12, X=2000, seed=111),
+           dict(model="potts", q=10, L=16, n_windows=8, m=4, kfinal=12, X=2000, seed=112),
+           dict(model="potts", q=4, L=12, n_windows=3, m=16, kfinal=12, X=2000, seed=113),
+           dict(model="ising", L=24, n_windows=8, m=2, kfinal=12, X=2000, seed=114),
+           dict(model="ising", L=8, n_windows=4, m=4, kfinal=8, X=2000, seed=115)]
+    g = rw.Rewl([rw.make_config(**kw) for kw in kws], tune=_tune(rw, kind, graph=1, poll=3))
+    orcs = [O.Sim(O.make_config(**kw)) for kw in kws]
+    for _ in range(20):
+        g.run(3)
+        for i, o in enumerate(orcs):
+            o.run(3)
+            assert_same(g.state(i), o.state(), f"graph {kind} instance {i}")
+    for i, o in enumerate(orcs):
+        assert np.array_equal(g.stats(i)["round_trips"], o.replicas()["round_trips"])
+    g.close()
+
+
+def test_batch64_graph_replay_autotuned(rw):
+    """The 64-instance batch, autotuned, four intervals replayed from its captured graph."""
+    from paper_1407_5140_amd import workloads as W
+    kws = W.batch()
+    g = rw.Rewl([rw.make_config(**kw) for kw in kws], tune=rw.make_tune(autotune=1, use_graph=1, poll_every=2))
+    assert g.tune()["use_graph"] == 1
+    orcs = [O.Sim(O.make_config(**kw)) for kw in kws]
+    for _ in range(2):
+        g.run(2)
+        for i, o in enumerate(orcs):
+            o.run(2)
+            assert_same(g.state(i), o.state(), f"batch instance {i} t={o.t}")
+    g.close()
+
+
+# ------------------------------------------------------- counts past 2^32
+def _ckpt_H_offset(rw, g, cfg):
+    """Byte offset and shape of the first instance's H array inside a checkpoint."""
+    W, WB, lo, hi = rw.rewl_layout(cfg)
+    S, N = cfg.n_windows * cfg.walkers_per_window, cfg.L * cfg.L
+    lat = cfg.L * ((cfg.L + 63) // 64) * S * 8 if cfg.model == 0 else N * S
+    return 16 + lat + S * 4, (S, WB)
+
+
+@pytest.mark.parametrize("kind", ["lane", "wave"])
+def test_counts_past_2_32_bitwise(rw, kind):
+    """Every walker's counts raised by C = 2^32 + 2^31 + 12345 at every occurring level
+    of its window (the oracle's ln g raised by C 2^-k to match), written into a
+    checkpoint and restored: the run continues bit-exact with counts above 2^32.
+    Eq. (8) with a = 2^20 keeps every window from merging at ln f = 2^-30."""
+    kw = dict(model="potts", q=5, L=8, n_windows=3, m=4, k0=30, kfinal=34, X=1500, seed=71,
+              flat_rule="visits", flat=(1 << 20, 1))
+    gc, oc = _cfgs(rw, **kw)
+    g = rw.Rewl([gc], tune=_tune(rw, kind))
+    orc = O.Sim(oc)
+    g.run(3)
+    orc.run(3)
+    assert_same(g.state(), orc.state(), "before")
+    C = (1 << 32) + (1 << 31) + 12345
+    W, WB, lo, hi = rw.rewl_layout(gc)
+    mask = rw.rewl_mask(gc)
+    occ = np.zeros((kw["n_windows"] * kw["m"], WB), bool)
+    for s in range(occ.shape[0]):
+        a = s // kw["m"]
+        occ[s, : hi[a] - lo[a] + 1] = mask[lo[a]:hi[a] + 1] > 0
+    blob = bytearray(rw.rewl_checkpoint(g.h))
+    off, shape = _ckpt_H_offset(rw, g, gc)
+    H = np.frombuffer(bytes(blob[off:off + 8 * shape[0] * shape[1]]), np.uint64).reshape(shape).copy()
+    H[occ] += np.uint64(C)
+    blob[off:off + H.nbytes] = H.tobytes()
+    rw.rewl_restore(g.h, bytes(blob))
+    st = orc.state()
+    k = st["k"][np.arange(occ.shape[0]) // kw["m"]]
+    orc.set_tables(np.where(occ, st["H"] + C, st["H"]),
+                   np.where(occ, st["lng"] + np.ldexp(float(C), -k)[:, None], st["lng"]))
+    assert_same(g.state(), orc.state(), "restored")
+    for _ in range(4):
+        g.run(5)
+        orc.run(5)
+        assert_same(g.state(), orc.state(), f"t={orc.t}")
+    assert g.state()["H"].min(initial=C, where=occ) >= C
+
+
+def test_count_spread_past_2_32_is_reported(rw):
+    """One level of one walker raised by 2^32: the walker's counts now spread over more
+    than the 32-bit range that a sweep keeps per level, and the run stops with
+    REWL_E_OVERFLOW instead of continuing on wrapped counts."""
+    kw = dict(model="ising", L=8, n_windows=2, m=2, k0=10, kfinal=20, X=500, seed=73)
+    gc = rw.make_config(**kw)
+    g = rw.Rewl([gc])
+    g.run(2)
+    blob = bytearray(rw.rewl_checkpoint(g.h))
+    off, shape = _ckpt_H_offset(rw, g, gc)
+    H = np.frombuffer(bytes(blob[off:off + 8 * shape[0] * shape[1]]), np.uint64).reshape(shape).copy()
+    H[0, 0] += np.uint64(1 << 32)
+    blob[off:off + H.nbytes] = H.tobytes()
+    rw.rewl_restore(g.h, bytes(blob))
+    with pytest.raises(rw.RewlError) as e:
+        g.run(2)
+    assert e.value.status == -5

@@ -55,15 +55,34 @@ def test_warm_start_converges_in_fewer_intervals(trained):
 
 
 def test_warm_start_keeps_accuracy(trained, golden):
+    """Warm (k0 = 8) and plain (k0 = 0) runs of Ising L=24 to ln f = 2^-13, three seeds
+    each, judged against the exact DOS: the mean relative error of ln g over the
+    levels that occur, and the largest absolute error of ln g where ln g > 10 (the
+    relative error at the two ground levels, ln g = ln 2, is not a useful scale).
+    Bounds: every run within 1e-2 mean and 2.0 absolute (plain runs of this size
+    reach 2.4e-3..7.4e-3 and 0.5..1.1), and the warm runs' median mean error within
+    1.5x of the plain runs' median."""
     Wm, net = trained
-    kw = dict(model="ising", q=2, L=24, n_windows=4, m=8, kfinal=13, X=2000, seed=1)
+    kw = dict(model="ising", q=2, L=24, n_windows=4, m=8, kfinal=13, X=2000)
     exact = golden.lng("ising_L24_lng.txt")
     ok = np.isfinite(exact)
+    big = exact[ok] > 10
     errs = {}
     for mode, k0, table in (("warm", 8, Wm.warm_table(net, kw)), ("plain", 0, None)):
-        n, lng = _intervals(Wm, dict(kw, k0=k0), table)
-        assert np.array_equal(np.isfinite(lng), ok)
-        errs[mode] = (n, float(np.max(np.abs(lng[ok] - exact[ok]) / np.abs(exact[ok]))))
-    print(f"[warm] Ising L=24 (intervals, max relative ln g error): {errs}")
-    # the warm start ends at the same resolution as the flat start
-    assert errs["warm"][1] < max(2 * errs["plain"][1], 5e-3)
+        kws = [dict(kw, k0=k0, seed=s) for s in (1, 2, 3)]
+        g, res = Wm.run_to_convergence(kws, 300.0, warm_tables=[table] * 3 if table is not None else None,
+                                       poll=10)
+        assert all(r["converged"] for r in res), (mode, res)
+        errs[mode] = []
+        for i in range(3):
+            lng = g.concat(i)[0]
+            assert np.array_equal(np.isfinite(lng), ok)
+            d = np.abs(lng[ok] - exact[ok])
+            errs[mode].append((res[i]["intervals"], float(np.mean(d / np.abs(exact[ok]))), float(d[big].max())))
+        g.close()
+    print(f"[warm] Ising L=24 to 2^-13 (intervals, mean relative error, max |error| where ln g > 10): {errs}")
+    for mode in errs:
+        for n, mean_eps, dmax in errs[mode]:
+            assert mean_eps < 1e-2 and dmax < 2.0, (mode, n, mean_eps, dmax)
+    med = {mode: float(np.median([e[1] for e in errs[mode]])) for mode in errs}
+    assert med["warm"] < 1.5 * med["plain"], med

@@ -277,13 +277,10 @@ def test_frozen_weights_sample_g_over_gw(golden):
         assert np.all(np.abs(obs[big] / p[big] - 1) < 0.05)
 
 
-def test_exchange_keeps_stationary_marginals(golden):
-    """Two windows with different fixed weights, an exchange every 2 attempts.
-
-    Under Eq. (1) the joint law is the product of each walker's g/g_w law, so each
-    walker's visit histogram keeps its single-walker marginal.  The two windows'
-    weights differ inside the overlap, so Eq. (1) is not trivially 1 there.
-    """
+def _exchange_marginals(golden):
+    """Two windows with different fixed weights, an exchange every 2 attempts; returns
+    the exchange counters and, per walker, the largest relative deviation of its visit
+    histogram from its single-walker law g/g_w over the levels holding > 2 %."""
     lg = X.ln_g(golden.counts("ising_q2_L4_counts.txt"))
     c = O.make_config("ising", L=4, n_windows=2, overlap=(3, 4), m=2, X=2, k0=39, kfinal=40,
                       flat=(1, 1), seed=31)
@@ -299,15 +296,24 @@ def test_exchange_keeps_stationary_marginals(golden):
         tabs.append(t)
     sim.run(400000)
     st = sim.state()
-    stats = sim.stats()
-    assert stats["ex_acc"][0] > 1000 and stats["ex_acc"][0] < stats["ex_prop"][0]
+    dev = []
     for sl in range(4):
         a = sl // 2
         p = _stationary(lg, tabs[a], lo[a], hi[a], mask)
         H = st["H"][sl].astype(float)
         obs = H / H.sum()
         big = p > 0.02
-        assert np.all(np.abs(obs[big] / p[big] - 1) < 0.06), (sl, obs, p)
+        dev.append(float(np.max(np.abs(obs[big] / p[big] - 1))))
+    return sim.stats(), dev
+
+
+def test_exchange_keeps_stationary_marginals(golden):
+    """Under Eq. (1) the joint law is the product of each walker's g/g_w law, so each
+    walker's visit histogram keeps its single-walker marginal.  The two windows'
+    weights differ inside the overlap, so Eq. (1) is not trivially 1 there."""
+    stats, dev = _exchange_marginals(golden)
+    assert stats["ex_acc"][0] > 1000 and stats["ex_acc"][0] < stats["ex_prop"][0]
+    assert max(dev) < 0.06, dev
 
 
 # ------------------------------------------------------- concatenation (A16)
@@ -448,3 +454,122 @@ def test_unequal_windows_converge_to_exact_ising_L8(golden):
 def test_bad_explicit_windows_rejected(lo, hi):
     with pytest.raises(ValueError):
         O.Sim(O.make_config("ising", L=8, n_windows=3, windows=(lo, hi)))
+
+
+# ------------------------------------------------------ 80 % flatness (A4)
+def _mean_rule(H, mask_w, num, den):
+    """Sec. II.A on one walker's counts, in Python integers: min H >= (num/den) mean H."""
+    v = [int(x) for x, ok in zip(H, mask_w) if ok]
+    return den * min(v) * len(v) >= num * sum(v), den * min(v) * len(v) == num * sum(v)
+
+
+def test_mean_rule_latches_exactly_80_percent():
+    """The latched flag equals 'the 80 % rule held at some interval end since the last
+    merge', with the non-strict comparison of "may not be smaller than 80 % of the
+    mean" (Sec. II.A).  Windows of three bins and a few attempts per interval make
+    exact equality 5 min n = 4 sum occur, which tells >= from >."""
+    W = 17                                        # Ising L = 4: bins 0..16
+    lo = list(range(0, 16, 2))
+    hi = [b + 2 for b in lo]
+    cfg = O.make_config("ising", L=4, n_windows=len(lo), m=4, kfinal=30, X=3, seed=5,
+                        windows=(lo, hi))
+    sim = O.Sim(cfg)
+    mask = O.mask_rule(cfg)
+    assert mask.size == W
+    h, m = len(lo), 4
+    latched = np.zeros(h * m, bool)
+    prev_k = sim.state()["k"].copy()
+    checked = ties = 0
+    for _ in range(3000):
+        sim.run(1)
+        st = sim.state()
+        for a in range(h):
+            if st["done"][a]:
+                continue
+            if st["k"][a] != prev_k[a]:           # merged: flags and counts start over
+                assert not st["flat"][a * m:(a + 1) * m].any()
+                latched[a * m:(a + 1) * m] = False
+                continue
+            mw = mask[lo[a]:hi[a] + 1]
+            for r in range(m):
+                sl = a * m + r
+                ok, tie = _mean_rule(st["H"][sl][: hi[a] - lo[a] + 1], mw, 4, 5)
+                if tie and not latched[sl]:
+                    ties += 1                     # only >= latches here
+                latched[sl] |= ok
+                assert bool(st["flat"][sl]) == latched[sl], (a, r, st["H"][sl])
+                checked += 1
+        prev_k = st["k"].copy()
+    assert checked > 10000 and ties >= 10
+
+
+# ------------------------------------------------------- exchange, planted mistakes
+@pytest.mark.parametrize("mode", [1, 2, 3], ids=["always-accept", "sign-flip", "dropped-term"])
+def test_exchange_marginal_check_fails_on_planted_mistakes(golden, mode):
+    """The marginal test of Eq. (1) above must fail when the oracle's exchange rule is
+    wrong: accepting every proposal, flipping the sign of the log ratio, or dropping
+    walker j's factor each bias the walkers' visit histograms well past the 6 %
+    tolerance that the correct rule meets."""
+    try:
+        O.exchange_mutation(mode)
+        stats, dev = _exchange_marginals(golden)
+    finally:
+        O.exchange_mutation(0)
+    assert stats["ex_acc"][0] > 1000
+    assert max(dev) > 0.15, dev
+
+
+# ------------------------------------------------------------ round trips (R29)
+def _recount_round_trips(windows_by_interval):
+    """Round trips of each replica from its window after every interval: a visit to
+    window 0, then one to window h-1, then one to window 0 again (Sec. IV.A)."""
+    seq = np.asarray(windows_by_interval)        # (intervals + 1, replicas)
+    h_top = seq.max()
+    out = []
+    for r in range(seq.shape[1]):
+        trips, seen0, seen_top = 0, False, False
+        for w in seq[:, r]:
+            if w == 0:
+                if seen0 and seen_top:
+                    trips += 1
+                seen0, seen_top = True, False
+            elif w == h_top and seen0:
+                seen_top = True
+        out.append(trips)
+    return np.array(out)
+
+
+@pytest.mark.parametrize("h,m,exchange", [(4, 2, True), (3, 4, True), (2, 1, True), (4, 2, False)])
+def test_round_trips_match_replica_trajectories(h, m, exchange):
+    """The oracle's round-trip counter against a recount from the windows each replica
+    visited interval by interval.  Each counted trip crosses every window pair once
+    upwards and once downwards, and an accepted exchange moves one replica each way,
+    so the accepted exchanges of every pair bound the total from above."""
+    cfg = O.make_config("ising", L=6, n_windows=h, m=m, k0=12, kfinal=30, X=60, seed=17,
+                        exchange=exchange)
+    sim = O.Sim(cfg)
+    S = h * m
+    traj = []
+
+    def windows_of_replicas():
+        rid = sim.replicas()["rid"]
+        w = np.empty(S, np.int64)
+        w[rid] = np.arange(S) // m                # replica rid[s] sits in window s // m
+        return w
+
+    traj.append(windows_of_replicas())
+    assert np.array_equal(np.sort(sim.replicas()["rid"]), np.arange(S))
+    for _ in range(3000):
+        sim.run(1)
+        traj.append(windows_of_replicas())
+    rt = sim.replicas()["round_trips"]
+    assert np.array_equal(np.sort(sim.replicas()["rid"]), np.arange(S))   # a permutation
+    if h > 1:                                     # the top window index is h - 1
+        assert np.array(traj).max() == h - 1
+    assert np.array_equal(rt, _recount_round_trips(traj))
+    if h > 1:
+        assert rt.sum() <= sim.stats()["ex_acc"][: h - 1].min()
+    if exchange:
+        assert rt.sum() > 20
+    else:
+        assert rt.sum() == 0
