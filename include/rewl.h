@@ -179,6 +179,19 @@ rewl_status rewl_get_window_lng(rewl_handle* h, int32_t instance, int32_t window
  * (h-1 entries, may be NULL) receives the join bins.  Runs on the device.      */
 rewl_status rewl_concat(rewl_handle* h, int32_t instance, double* out_lng, int32_t* join);
 
+/* rewl_concat for callers that cannot allocate device memory (code that must not
+ * call hipMalloc: graph-capturing or tight serving loops, harnesses that forbid
+ * it).  Same inputs, outputs and result as rewl_concat; its device staging lives
+ * in a fixed 256 KiB array of device memory that each GPU holds from library
+ * load until the process ends, so the call makes no allocation.  Limit: 8 W +
+ * 12 h bytes (plus alignment) must fit 256 KiB, e.g. W <= 32 000 bins for a
+ * few hundred windows (every Ising lattice up to L = 128, Potts up to L = 126);
+ * larger instances get REWL_E_INVALID before any device work.  The array is
+ * shared by every call on one GPU: calls from threads of one process are
+ * serialised by the library; calls that overlapped on one GPU would race.  The
+ * handle's device must be the current device (REWL_E_INVALID otherwise).       */
+rewl_status rewl_concat_noalloc(rewl_handle* h, int32_t instance, double* out_lng, int32_t* join);
+
 /* Error analysis over n independent runs (Sec. II.B).  runs[0..n) are instances
  * of the handle with equal model, q, L and windows (normally differing only in
  * seed); each supplies one piece per window, its rewl_get_window_lng table.

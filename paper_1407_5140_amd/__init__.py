@@ -85,6 +85,7 @@ _sigs = {
     "rewl_run_exact": ([_vp, ctypes.c_int64], ctypes.c_int),
     "rewl_get_window_lng": ([_vp, ctypes.c_int32, ctypes.c_int32, _vp], ctypes.c_int),
     "rewl_concat": ([_vp, ctypes.c_int32, _vp, _vp], ctypes.c_int),
+    "rewl_concat_noalloc": ([_vp, ctypes.c_int32, _vp, _vp], ctypes.c_int),
     "rewl_ensemble": ([_vp, _vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, _vp, _vp], ctypes.c_int),
     "rewl_thermo": ([ctypes.c_int32, ctypes.c_int32, _vp, ctypes.c_int32, _vp, ctypes.c_int32, _vp, _vp,
                      _vp], ctypes.c_int),
@@ -240,6 +241,14 @@ def rewl_concat(h, instance: int, W: int, n_windows: int):
     out = np.empty(W, np.float64)
     join = np.zeros(max(n_windows - 1, 1), np.int32)
     _check(_lib.rewl_concat(h, instance, _p(out), _p(join)), "rewl_concat")
+    return out, join[: max(n_windows - 1, 0)]
+
+
+def rewl_concat_noalloc(h, instance: int, W: int, n_windows: int):
+    """rewl_concat staged in the library's fixed device array (no allocation)."""
+    out = np.empty(W, np.float64)
+    join = np.zeros(max(n_windows - 1, 1), np.int32)
+    _check(_lib.rewl_concat_noalloc(h, instance, _p(out), _p(join)), "rewl_concat_noalloc")
     return out, join[: max(n_windows - 1, 0)]
 
 

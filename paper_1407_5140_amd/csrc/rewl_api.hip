@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -147,6 +148,7 @@ struct HostInst {
 }  // namespace
 
 struct rewl_handle {
+    int device = 0;             // the device current at creation (owns every buffer)
     hipStream_t stream = nullptr;
     bool own_stream = false;
     int n = 0;
@@ -455,6 +457,7 @@ static rewl_status create_impl(const rewl_config* cfgs, int32_t n, void* hip_str
     if (tune && tune->guard_band_log2 != 0 && (tune->guard_band_log2 < -40 || tune->guard_band_log2 > -2))
         return fail(REWL_E_INVALID, "guard_band_log2 must be 0 (2^-40) or in [-40, -2]");
     rewl_handle* H = new rewl_handle();
+    H->device = dev;
     if (tune) H->tune = *tune;
     if (H->tune.poll_every <= 0) H->tune.poll_every = 8;
     const double band = H->tune.guard_band_log2 ? std::ldexp(1.0, H->tune.guard_band_log2) : kBand;
@@ -934,6 +937,74 @@ rewl_status rewl_concat(rewl_handle* H, int32_t i, double* out_lng, int32_t* joi
     if (e == hipSuccess) e = hipMemcpyAsync(&status, d_status.p, 4, hipMemcpyDeviceToHost, H->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(H->stream);
     if (e != hipSuccess) return fail(REWL_E_DEVICE, std::string("concat: ") + hipGetErrorString(e));
+    if (status != 0) return fail(REWL_E_STATE, "no valid join point in some overlap");
+    return REWL_OK;
+}
+
+// ---- concatenation without allocation.  Its device staging (the joined row,
+// the pieces' shifts, the join bins and a status word) lives in `scratch`, a
+// fixed array in device memory: every GPU the library runs on holds its own
+// copy from load until the process ends.  Host code never uses the array's name
+// as a device address; the address is looked up once per device.
+constexpr size_t kScratchBytes = size_t(256) << 10;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;                 // guards the lookup table and serialises calls
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on `dev` (current), looked up on first use.
+rewl_status scratch_ptr(int dev, void** out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return fail(REWL_E_DEVICE, "device index out of range");
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(REWL_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return REWL_OK;
+}
+}  // namespace
+
+rewl_status rewl_concat_noalloc(rewl_handle* H, int32_t i, double* out_lng, int32_t* join)
+{
+    rewl_status s = check_inst(H, i);
+    if (s != REWL_OK) return s;
+    if (!out_lng) return fail(REWL_E_INVALID, "null output");
+    const HostInst& hi = H->inst[i];
+    const size_t nj = (size_t)std::max(hi.h - 1, 1);
+    const size_t off_shift = ((size_t)hi.W * 8 + 255) & ~size_t(255);
+    const size_t off_join = off_shift + (((size_t)hi.h * 8 + 255) & ~size_t(255));
+    const size_t off_status = off_join + ((nj * 4 + 255) & ~size_t(255));
+    if (off_status + 4 > kScratchBytes)
+        return fail(REWL_E_INVALID, "rewl_concat_noalloc: " + std::to_string(hi.W) + " bins and " +
+                                        std::to_string(hi.h) + " windows need " + std::to_string(off_status + 4) +
+                                        " bytes of staging, above its fixed " + std::to_string(kScratchBytes) +
+                                        " (use rewl_concat)");
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != H->device) return fail(REWL_E_INVALID, "the handle's device is not the current device");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    char* base = nullptr;
+    if ((s = scratch_ptr(dev, (void**)&base)) != REWL_OK) return s;
+    double* d_out = (double*)base;
+    double* d_shift = (double*)(base + off_shift);
+    int32_t* d_join = (int32_t*)(base + off_join);
+    int32_t* d_status = (int32_t*)(base + off_status);
+    int32_t status = 0;
+    // k_concat writes every entry it later reads (status and shift[0] first)
+    hipLaunchKernelGGL(k_concat, dim3(1), dim3(256), 0, H->stream, H->d_insts, i, hi.dev.base, d_out, d_join,
+                       d_shift, d_status);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(out_lng, d_out, (size_t)hi.W * 8, hipMemcpyDeviceToHost, H->stream));
+    if (join && hi.h > 1)
+        HIP_TRY(hipMemcpyAsync(join, d_join, (size_t)(hi.h - 1) * 4, hipMemcpyDeviceToHost, H->stream));
+    HIP_TRY(hipMemcpyAsync(&status, d_status, 4, hipMemcpyDeviceToHost, H->stream));
+    HIP_TRY(hipStreamSynchronize(H->stream));
     if (status != 0) return fail(REWL_E_STATE, "no valid join point in some overlap");
     return REWL_OK;
 }
