@@ -49,7 +49,8 @@ LABELS = {
 
 
 # rocprofv3 summaries holding the HBM byte counters of a workload's sweep kernel
-PROFILES = {"ising64": "k_sweep_wave_ising_L64.txt", "potts32": "k_sweep_wave_potts_q10_L32.txt"}
+PROFILES = {"ising64": "k_sweep_wave_ising_L64.txt", "potts32": "k_sweep_wave_potts_q10_L32.txt",
+            "batch64": "k_sweep_k_rng_batch64_lane_lds53.txt"}
 KERNEL_SOURCES = ("paper_1407_5140_amd/csrc/rewl_kernels.hip", "paper_1407_5140_amd/csrc/rewl_device.hpp")
 
 
@@ -497,6 +498,8 @@ def main(argv=None):
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="default run only: skip the batch throughput and the Ising L=8 time-to-converge keys")
     ap.add_argument("--sweep", default="auto", choices=["auto", "lane", "wave"])
     ap.add_argument("--converge", action="store_true",
                     help="run to convergence and print time-to-converge and DOS error")
@@ -506,6 +509,8 @@ def main(argv=None):
                     help="only copy a device buffer of this size and exit (a kernel of known "
                          "traffic for scaling the HBM byte counters)")
     ap.add_argument("--wpb", type=int, default=0, help="walkers per block (0 = library choice)")
+    ap.add_argument("--lds-kb", type=int, default=0,
+                    help="lane sweep: cap on a tile's LDS in KiB (0 = the device limit)")
     ap.add_argument("--flat-rule", default="mean", choices=["mean", "visits"],
                     help="--converge: flatness rule (mean: min H >= num/den of the mean; "
                          "visits: H >= (num/den)/sqrt(ln f) for every level, Eq. (8))")
@@ -615,7 +620,8 @@ def main(argv=None):
     S = sum(kw["n_windows"] * kw["m"] for kw in kws)
     att_step = sum(kw["n_windows"] * kw["m"] * kw["X"] for kw in kws)
     t_create = time.perf_counter()
-    tune = rw.make_tune(args.sweep, args.wpb, 0, 1 << 20, autotune=1 if args.autotune else 0)
+    tune = rw.make_tune(args.sweep, args.wpb, 0, 1 << 20, lds_target_kb=args.lds_kb,
+                        autotune=1 if args.autotune else 0)
     g = rw.Rewl(cfgs, tune=tune)
     t_create = time.perf_counter() - t_create
     info = g.info()
@@ -669,11 +675,56 @@ def main(argv=None):
         "sweep_attempts_per_s": att_step / (sweep_ms * 1e-3),
     }
     g.close()
+    if args.workload == "ising64" and not args.no_extras and not args.autotune:
+        out["batch64"] = batch_line(rw)
+        out["time_to_converge"] = ising8_converge(rw)
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on the host cores", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(kws, args.cpu_budget)
     print(json.dumps(out), flush=True)
     return 0
+
+
+def batch_line(rw, steps: int = 10, warmup: int = 2) -> dict:
+    """The 64-instance batch, autotuned, timed like the main workload (extra keys)."""
+    kws = workload("batch64")
+    t0 = time.perf_counter()
+    g = rw.Rewl([rw.make_config(**kw) for kw in kws], tune=rw.make_tune(autotune=1, poll_every=1 << 20))
+    t_create = time.perf_counter() - t0
+    rw.rewl_run_exact(g.h, warmup)
+    rw.rewl_set_timing(g.h, True)
+    st0 = g.stats()
+    t0 = time.perf_counter()
+    rw.rewl_run_exact(g.h, steps)
+    dt = time.perf_counter() - t0
+    st1 = g.stats()
+    att = steps * sum(kw["n_windows"] * kw["m"] * kw["X"] for kw in kws)
+    ops = steps * sum(OPS_PER_ATTEMPT[kw["model"]] * kw["n_windows"] * kw["m"] * kw["X"] for kw in kws)
+    sweep_ms = (st1["sweep_ms"] - st0["sweep_ms"]) / steps
+    interval_ms = (st1["interval_ms"] - st0["interval_ms"]) / steps
+    info, tune = g.info(), g.tune()
+    g.close()
+    print(f"[bench] batch64: {att / dt:.4g} attempts/s, sweep {sweep_ms:.3f} ms/launch, interval "
+          f"{interval_ms:.3f} ms, tune {tune}, create+autotune {t_create:.2f} s", file=sys.stderr, flush=True)
+    return {"workload": LABELS["batch64"], "attempts_per_s": att / dt, "ms_per_step": dt * 1e3 / steps,
+            "steps": steps, "sweep_ms": sweep_ms, "interval_ms": interval_ms,
+            "sweep": info["sweep_kind"], "lds_target_kb": tune["lds_target_kb"],
+            "roofline": {"bound": "alu", "achieved": ops / steps / (sweep_ms * 1e-3) / 1e12,
+                         "peak": PEAK_LANE_OPS / 1e12, "unit": "Tops/s",
+                         "frac": ops / steps / (sweep_ms * 1e-3) / PEAK_LANE_OPS,
+                         "kernel": "k_sweep" if info["sweep_kind"] == "lane" else "k_sweep_wave"}}
+
+
+def ising8_converge(rw, seeds=(1, 2, 3)) -> dict:
+    """Time to converge of the Ising L=8 workload (4 windows, one walker each, ln f 1 ->
+    2^-20 <= 1e-6), seeds run one after another, with the DOS error against the exact DOS."""
+    from paper_1407_5140_amd import workloads as W
+    kw0 = W.single("ising8")
+    res = [converge(rw, kw0, LABELS["ising8"], rw.make_tune(poll_every=25), 60.0, sd) for sd in seeds]
+    return {"workload": LABELS["ising8"], "seeds": list(seeds),
+            "seconds": [r["seconds"] for r in res], "intervals": [r["intervals"] for r in res],
+            "converged": [r["converged"] for r in res],
+            "eps_mean": [r.get("eps_mean") for r in res], "eps_max": [r.get("eps_max") for r in res]}
 
 
 if __name__ == "__main__":

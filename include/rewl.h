@@ -35,10 +35,13 @@ typedef enum {
     REWL_E_NOMEM = -3,        /* device or host allocation failed                  */
     REWL_E_DEVICE = -4,       /* a HIP call failed                                  */
     REWL_E_OVERFLOW = -5,     /* the exact-FP64 budget would overflow, or a walker's
-                                 counts since its last merge spread over more than
-                                 2^32 - X (its highest count minus its lowest over the
-                                 levels of its window that occur: a walker stuck on a
-                                 few levels); the handle's state is then undefined   */
+                                 counts since its last merge (64-bit, no ceiling of
+                                 their own) spread too far for one interval: every
+                                 count of an occurring level of its window must lie
+                                 within 2^31 below and 2^31 - X above the count of
+                                 the level it sits at (H >= 2^31 of a level means
+                                 ~10^12 attempts of one walker without a merge); the
+                                 handle's state is then undefined                   */
     REWL_E_INIT_STUCK = -6,   /* a walker could not be driven into its window       */
     REWL_E_STATE = -7         /* call not valid in the handle's current state       */
 } rewl_status;

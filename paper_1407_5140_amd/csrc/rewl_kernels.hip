@@ -123,13 +123,14 @@ __device__ void sweep_tile(const Inst& I, const Tile& tile, char* smem)
     const int lnw = __builtin_ctz(nw);                           // nw is a power of two
 
     // ---- stage the window table, the tile's histograms and lattices in LDS.
-    //      A walker's counts enter LDS relative to its own smallest count over
-    //      the levels of the window that occur (cw, kept by lane l for walker l):
-    //      every decision of the sweep compares two ln g values of one walker,
-    //      so a per-walker constant cancels, and the 32-bit LDS entries only
-    //      need to hold the spread of the counts, not their size.  Levels that
-    //      never occur carry the sentinel 0xffffffff (never visited, excluded
-    //      from the flatness minimum, written back as 0).
+    //      A walker's counts enter LDS relative to an offset cw of its own (kept by
+    //      lane l for walker l): every decision of the sweep compares two ln g
+    //      values of one walker, so a per-walker constant cancels, and the 32-bit
+    //      LDS entries only need to hold the counts' spread around the offset.
+    //      cw = H(current bin) - 2^31 when that count is past 2^31, else 0 (so
+    //      counts below 2^31 enter as they are).  Levels that never occur carry
+    //      the sentinel 0xffffffff (never visited, excluded from the flatness
+    //      minimum, written back as 0).
     // bins b >= width (a window narrower than WB) are outside the window: +inf
     // table (moves there are rejected) and the never-visited sentinel
     const int width = I.hi[a] - lo + 1;
@@ -138,35 +139,32 @@ __device__ void sweep_tile(const Inst& I, const Tile& tile, char* smem)
         lbase[i] = (b >= 0 && b < width) ? I.base[(size_t)a * WB + b] : __builtin_inf();
     }
     uint64_t cw = 0;
-    for (int l = 0; l < nw; ++l) {
-        uint64_t mn = ~0ull, mx = 0;
-        for (int b = lane; b < width; b += nthr)
-            if (I.mask[lo + b]) {
-                const uint64_t v = I.H[(size_t)(slot0 + l) * WB + b];
-                mn = v < mn ? v : mn;
-                mx = v > mx ? v : mx;
-            }
-        for (int off = 32; off > 0; off >>= 1) {
-            const uint64_t m2 = shfl_xor_u64(mn, off), x2 = shfl_xor_u64(mx, off);
-            mn = m2 < mn ? m2 : mn;
-            mx = x2 > mx ? x2 : mx;
-        }
-        if (lane == l) cw = mn;
-        // the spread plus this interval's X updates must stay below the sentinel
-        if (lane == 0 && mx - mn >= 0xffffffffull - (uint64_t)I.X) atomicOr(&I.ctr->err, kErrOverflow);
+    if (lane < nw) {
+        const uint64_t hc0 = I.H[(size_t)(slot0 + lane) * WB + (I.bin[slot0 + lane] - lo)];
+        cw = hc0 > (1ull << 31) ? hc0 - (1ull << 31) : 0ull;
     }
+    // counts must lie in [cw, cw + 2^32 - 1 - X) so that this interval's X
+    // updates stay below the sentinel; otherwise the run reports an overflow
+    const uint64_t span = 0xffffffffull - (uint64_t)I.X;
     // global H is walker-major: H[slot][bin]; consecutive threads take consecutive bins
+    bool bad = false;
     for (int l = 0; l < nw; ++l) {
         const uint64_t cl = rl64(cw, l);
         for (int i = lane; i < nbins; i += nthr) {
             const int b = i - kPad;
             uint32_t hv = 0;
-            if (b >= 0 && b < WB)
-                hv = (b < width && I.mask[lo + b]) ? (uint32_t)(I.H[(size_t)(slot0 + l) * WB + b] - cl)
-                                                    : 0xffffffffu;
+            if (b >= 0 && b < WB) {
+                hv = 0xffffffffu;
+                if (b < width && I.mask[lo + b]) {
+                    const uint64_t v = I.H[(size_t)(slot0 + l) * WB + b] - cl;   // wraps if below cl
+                    bad |= v >= span;
+                    hv = (uint32_t)v;
+                }
+            }
             lH[(i << lnw) + l] = hv;
         }
     }
+    if (bad) atomicOr(&I.ctr->err, kErrOverflow);
     // lattices are walker-major too: lat[slot][word] / plat[slot][site]
     if (MODEL == 0) {
         uint64_t* lat = (uint64_t*)latp;
@@ -461,31 +459,28 @@ __device__ void sweep_wave(const Inst& I, const Tile& tile, char* smem)
     uint64_t* lrow = (uint64_t*)(smem + off_map + (size_t)G * M * 8) + (size_t)wave * L * wpr;
     // site -> map entry: the site itself when every site has one, else site mod 4096
     auto ent = [&](int site) { return WIDE ? (site & (kWaveMapMax - 1)) : site; };
-    // the walker's counts relative to its smallest over the occurring levels
-    // (a per-walker constant cancels from every decision), see sweep_tile
+    // the walker's counts relative to an offset of its own (a per-walker constant
+    // cancels from every decision), chosen and checked as in sweep_tile
     uint64_t cw = 0;
     if (active) {
-        uint64_t mn = ~0ull, mx = 0;
-        for (int b = lane; b < width; b += 64)
-            if (I.mask[lo + b]) {
-                const uint64_t v = I.H[(size_t)slot * WB + b];
-                mn = v < mn ? v : mn;
-                mx = v > mx ? v : mx;
-            }
-        for (int off = 32; off > 0; off >>= 1) {
-            const uint64_t m2 = shfl_xor_u64(mn, off), x2 = shfl_xor_u64(mx, off);
-            mn = m2 < mn ? m2 : mn;
-            mx = x2 > mx ? x2 : mx;
-        }
-        cw = mn;
-        if (lane == 0 && mx - mn >= 0xffffffffull - (uint64_t)I.X) atomicOr(&I.ctr->err, kErrOverflow);
+        const uint64_t hc0 = I.H[(size_t)slot * WB + (I.bin[slot] - lo)];
+        cw = hc0 > (1ull << 31) ? hc0 - (1ull << 31) : 0ull;
+        const uint64_t span = 0xffffffffull - (uint64_t)I.X;
+        bool bad = false;
         for (int i = lane; i < nbins; i += 64) {
             const int b = i - kPad;
             uint32_t hv = 0;
-            if (b >= 0 && b < WB)
-                hv = (b < width && I.mask[lo + b]) ? (uint32_t)(I.H[(size_t)slot * WB + b] - cw) : 0xffffffffu;
+            if (b >= 0 && b < WB) {
+                hv = 0xffffffffu;
+                if (b < width && I.mask[lo + b]) {
+                    const uint64_t v = I.H[(size_t)slot * WB + b] - cw;
+                    bad |= v >= span;
+                    hv = (uint32_t)v;
+                }
+            }
             lH[i] = hv;
         }
+        if (bad) atomicOr(&I.ctr->err, kErrOverflow);
         for (int i = lane; i < M; i += 64) lmap[i] = 0;
         if (MODEL == 0) {
             for (int i = lane; i < L * wpr; i += 64) lrow[i] = I.lat[(size_t)slot * L * wpr + i];
@@ -526,7 +521,11 @@ __device__ void sweep_wave(const Inst& I, const Tile& tile, char* smem)
             lH[i] = (uint32_t)((gl - lbase[i]) * unscale);
     };
     load_window();
-    double lngc = rld(gl, idx);          // ln g of the current bin (wave-uniform)
+    // B + j incv is the walker's ln g at its current bin before attempt j of the
+    // chunk.  The register window's entry for that bin is left stale while the
+    // walker stays there (only attempts with d != 0 read the window) and is
+    // written when the walker leaves the bin or the window is stored.
+    double B = rld(gl, idx);
     const double laneinc = (double)lane * incv;
 
     for (int64_t j0 = 0; j0 < X; j0 += 64) {
@@ -557,88 +556,112 @@ __device__ void sweep_wave(const Inst& I, const Tile& tile, char* smem)
         evaluate();
         const double vbl = threshold_of(u53_of(x), band);
         const double vbl2 = vbl - 2.0 * band;     // below it a reject is certain
-        // earlier attempts of the chunk whose site lies in this attempt's neighbourhood
-        if (lane < n) atomicOr((unsigned long long*)&lmap[ent(site)], 1ull << lane);
-        const uint64_t pm = (lmap[ent(site)] | lmap[ent(s_up)] | lmap[ent(s_dn)] | lmap[ent(s_lf)] |
-                             lmap[ent(s_rt)]) &
-                            ((1ull << lane) - 1);
+        // attempts of the chunk at this attempt's site or one of its neighbours.
+        // Neighbourhoods are symmetric, so the later ones among them (qm) are
+        // exactly the attempts whose evaluation a flip of this one makes out of
+        // date, and the earlier ones (pm) those whose flip makes this one out of
+        // date.  (Sites sharing a map entry only add attempts to either set.)
+        const uint64_t lanebit = 1ull << lane;
+        if (lane < n) atomicOr((unsigned long long*)&lmap[ent(site)], lanebit);
+        const uint64_t nbh = lmap[ent(site)] | lmap[ent(s_up)] | lmap[ent(s_dn)] | lmap[ent(s_lf)] |
+                             lmap[ent(s_rt)];
         if (lane < n) lmap[ent(site)] = 0;
+        const uint64_t pm = nbh & (lanebit - 1);
+        const uint64_t qm = nbh & ~(lanebit | (lanebit - 1));
         const uint64_t live = n == 64 ? ~0ull : ((1ull << n) - 1);
-        uint64_t F = 0;                   // attempts flipped since the lanes last evaluated
-        // B = lngc - i incv: with it, lane j's ln g difference is B - gp + j incv
-        double B = lngc;
+        uint64_t* const fword = lrow + (WIDE ? rr * wpr + (cc >> 6) : rr);   // Ising: the flip's word
+        const uint64_t fbit = 1ull << (cc & 63);
+        // zall: moves within the bin (d = 0, always accepted); stale: attempts that
+        // are out of date by the time the chain reaches them -- an earlier d = 0
+        // move since the last evaluation lies in the neighbourhood (fixed at the
+        // evaluation), or an accepted move with d != 0 since then (added per move)
+        uint64_t zall, nzl, stale;
+        int d4;                           // byte offset of the candidate bin's lane from idx
+        auto classify = [&](int i0) {
+            d4 = d << 2;
+            zall = __builtin_amdgcn_ballot_w64(d == 0) & live;
+            nzl = ~zall & live;
+            stale = __builtin_amdgcn_ballot_w64((pm & zall & (~0ull << i0)) != 0) & live;
+        };
+        classify(0);
 
+        // the run loop; it leaves at the end of the chunk, and to move the
+        // register window when a move brings the walker within four bins of its
+        // edge (then it continues at attempt i)
         int i = 0;
-        while (i < n) {
-            const uint64_t run = live & (~0ull << i);
-            const int pos = idx + d;
+        for (;;) {
+            const uint64_t run = ~0ull << i;              // every mask below is within live
+            const double t = B + laneinc;                 // ln g of the bin, exact
+            const int pos4 = d4 + (idx << 2);
             const double gp = __builtin_bit_cast(
-                double, ((uint64_t)shfl32((uint32_t)(__builtin_bit_cast(uint64_t, gl) >> 32), pos) << 32) |
-                            shfl32((uint32_t)__builtin_bit_cast(uint64_t, gl), pos));
-            // ln g now - ln g of the candidate bin, exact
-            const double dl = (B - gp) + laneinc;
-            const uint64_t zall = __builtin_amdgcn_ballot_w64(d == 0);
+                double, ((uint64_t)(uint32_t)__builtin_amdgcn_ds_bpermute(
+                             pos4, (int)(uint32_t)(__builtin_bit_cast(uint64_t, gl) >> 32))
+                         << 32) |
+                            (uint32_t)__builtin_amdgcn_ds_bpermute(pos4, (int)(uint32_t)__builtin_bit_cast(uint64_t, gl)));
+            const double dl = t - gp;                     // ln g now - ln g of the candidate, exact
             const uint64_t gt = __builtin_amdgcn_ballot_w64(dl > vbl);
-            const uint64_t ge = __builtin_amdgcn_ballot_w64(dl >= vbl2);     // holds gt
-            const uint64_t zero = zall & run;
-            const uint64_t acc = gt & ~zall & run;
-            uint64_t amb = ge & ~gt & ~zall & run;
-            // out of date: an earlier flip (since the lanes evaluated, or a d = 0 move
-            // of this run) lies in the attempt's neighbourhood.  Accepted and out of
-            // date counts as out of date: it is re-evaluated before it is taken.
-            const uint64_t hit = __builtin_amdgcn_ballot_w64((pm & (zero | F)) != 0) & run;
-            const uint64_t stop = acc | hit;
-            int js = stop ? (int)__builtin_ctzll(stop) : n;
-            uint64_t below = (stop & (~stop + 1)) - 1;                     // lanes below js
-            bool move = ((acc & ~hit) >> js) & 1u;
-            // an attempt inside the guard band is decided exactly, in order
-            while (__builtin_expect((amb & below) != 0, 0)) {
-                const int kk = (int)__builtin_ctzll(amb);
-                amb &= amb - 1;
-                if (lane == 0) atomicAdd((unsigned long long*)&I.ctr->slow, 1ull);
-                if (__builtin_amdgcn_readfirstlane(
-                        slow_decide(I, T0 + (uint64_t)j0 + (uint64_t)kk, (uint32_t)slot, rld(dl, kk)) ? 1 : 0)) {
-                    js = kk;
-                    below = (1ull << kk) - 1;
-                    move = true;
-                }
+            const uint64_t ge = __builtin_amdgcn_ballot_w64(dl >= vbl2);    // holds gt
+            const uint64_t nzr = nzl & run;               // attempts with d != 0 from i on
+            const uint64_t acc = gt & nzr;
+            const uint64_t stop = acc | (stale & run);
+            uint64_t sbit = stop & (~stop + 1);           // the first stop, or 0
+            uint64_t below = sbit - 1;                    // lanes below it (all if none)
+            // accepted and out of date counts as out of date: re-evaluated first
+            uint64_t mv = sbit & acc & ~stale;            // the accepted move, or 0
+            // attempts inside the guard band are decided exactly, in order
+            uint64_t amb = ge & ~gt & nzr & below;
+            if (__builtin_expect(amb != 0, 0)) {
+                do {
+                    const int kk = (int)__builtin_ctzll(amb);
+                    amb &= amb - 1;
+                    if (lane == 0) atomicAdd((unsigned long long*)&I.ctr->slow, 1ull);
+                    if (__builtin_amdgcn_readfirstlane(
+                            slow_decide(I, T0 + (uint64_t)j0 + (uint64_t)kk, (uint32_t)slot, rld(dl, kk)) ? 1 : 0)) {
+                        sbit = mv = 1ull << kk;
+                        below = sbit - 1;
+                        break;
+                    }
+                } while (amb);
             }
-            // attempts i..js-1 were rejected or moved within the bin: the bin took
-            // js - i updates; the d = 0 moves among them and a move at js flip
-            const uint64_t flips = (zero & below) | (move ? (1ull << js) : 0ull);
-            if (flips) {
-                if ((flips >> lane) & 1u) {
-                    if (MODEL == 0)
-                        atomicXor((unsigned long long*)&lrow[WIDE ? rr * wpr + (cc >> 6) : rr],
-                                  1ull << (cc & 63));
-                    else llat[site] = (uint8_t)nv;
-                }
-                F |= flips;
+            // attempts i..js-1 were rejected or moved within the bin; the d = 0
+            // moves among them and an accepted move at js flip
+            const uint64_t flips = (zall & run & below) | mv;
+            if (flips && __builtin_amdgcn_inverse_ballot_w64(flips)) {
+                if (MODEL == 0) atomicXor((unsigned long long*)fword, fbit);
+                else llat[site] = (uint8_t)nv;
             }
-            const double jsinc = (double)js * incv;
-            if (lane == idx) gl = B + jsinc;
-            if (move) {
+            if (mv) {
+                const int js = (int)__builtin_ctzll(mv);
+                // the old bin after attempts up to js - 1 is t at lane js; the
+                // differences below are exact (multiples of 2^-k, small)
+                const double jsinc = rld(t, js) - B;      // js incv
+                if (lane == idx) gl = B + jsinc;
                 idx += __builtin_amdgcn_readlane(d, js);
+                stale |= rl64(qm, js);
+                // the new bin's entry lacks attempt js's update, so B = entry - js incv
                 B = rld(gl, idx) - jsinc;
-                if (lane == idx) gl += incv;
-                if (__builtin_expect(idx < 4 || idx > 59, 0)) {
+                i = js + 1;
+                if (__builtin_expect((unsigned)(idx - 4) > 55u, 0)) {   // idx < 4 or idx > 59
+                    // store the window with the bin's current value (B + i incv),
+                    // reload it around the walker; the entry may stay current
+                    if (lane == idx) gl = B + (double)i * incv;
                     store_window();
                     const int bb = b0 + idx;
                     b0 = bb - 32 < 0 ? 0 : (bb - 32 > b0max ? b0max : bb - 32);
                     idx = bb - b0;
                     load_window();
                 }
-                i = js + 1;
+                if (i >= n) break;
             } else {
-                i = js;
-                if (js < n) {             // attempt js is out of date: evaluate again
-                    evaluate();
-                    F = 0;
-                }
+                if (!stop) break;
+                i = (int)__builtin_ctzll(stop);           // attempt i is out of date
+                evaluate();
+                classify(i);
             }
         }
-        lngc = B + (double)n * incv;
+        B += (double)n * incv;
     }
+    if (lane == idx) gl = B;
     store_window();
 
     // ---- write back

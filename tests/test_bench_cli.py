@@ -23,7 +23,10 @@ def test_profiled_traffic_requires_matching_sources(monkeypatch):
     # counts) or it does not (None); a wrong kernel name never matches
     assert got is None or (len(got) == 2 and all(v > 0 for v in got))
     assert bench.profiled_traffic("ising64", "no_such_kernel") is None
-    assert bench.profiled_traffic("batch64", "k_sweep") is None
+    for k in ("k_sweep", "k_rng"):
+        got = bench.profiled_traffic("batch64", k)
+        assert got is None or (len(got) == 2 and all(v > 0 for v in got))
+    assert bench.profiled_traffic("potts100", "k_sweep_wave") is None     # no summary committed
 
 
 def test_ground_tilted_windows_are_a_valid_layout():
