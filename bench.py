@@ -43,6 +43,8 @@ LABELS = {
     "ising64": "2D Ising L=64 periodic, 16 windows o=3/4, 64 walkers/window, X=1e4",
     "potts32": "2D 10-state Potts L=32 periodic, 32 windows o=3/4, 128 walkers/window, X=1e4",
     "potts100": "2D 10-state Potts L=100 periodic, 77 windows of 1001 bins o=3/4, 8 walkers/window, X=1e4",
+    "ising128": "2D Ising L=128 periodic, 32 windows o=3/4, 64 walkers/window, X=1e4",
+    "potts64": "2D 10-state Potts L=64 periodic, 32 windows o=3/4, 128 walkers/window, X=1e4",
     "batch64": "64 independent REWL instances: Ising L 16-64 and Potts q 4/8/10 L 16-32, "
                "8-32 windows, 32-128 walkers/window, X=1e4",
 }
@@ -144,7 +146,8 @@ def converge(rw, kw: dict, label: str, tune, max_s: float, seed: int) -> dict:
     st = g.stats()
     out = {"workload": label, "seed": seed, "converged": bool(done), "seconds": dt,
            "intervals": st["intervals"], "attempts": st["attempts"], "min_k": st["min_k"],
-           "kfinal": kw["kfinal"]}
+           "kfinal": kw["kfinal"], "k": [int(v) for v in st["k"]], "round_trips": int(st["round_trips_total"]),
+           "ms_per_interval": dt * 1e3 / max(st["intervals"], 1)}
     if done:
         lng, join = g.concat()
         ex = exact_ln_g(kw)
@@ -489,6 +492,160 @@ def ensemble_cpu_baseline(kws, n, R, T, budget_s) -> dict:
     return res
 
 
+def headline_study(rw, args) -> dict:
+    """The warm-start comparison to ln f = 2^-27 (~1e-8) with the DOS error gate.
+
+    The network is trained on REWL's own results (ln f -> 2^-16) for Ising and
+    10-state Potts lattices smaller than the target, produced in this run.  The
+    target (Ising, exact DOS known) runs n seeds plain (ln f from 1) and n seeds
+    warm (the network's table, ln f from 2^-k0), each group in its own handle so
+    that each has the GPU to itself; time to converge = wall time until every
+    window of every seed of the group reached 2^-kfinal.  Accuracy: eps = |ln g^ -
+    ln g| / ln g over the levels that occur (max and mean), per run and for the
+    n-run mean of the pieces joined by the paper's rule (Sec. II.B), the gate
+    being max eps <= 5e-3."""
+    from paper_1407_5140_amd import warm as Wm
+    log = lambda m: print(f"[headline] {m}", file=sys.stderr, flush=True)
+    L, h, m, kf, n = args.hl_L, args.hl_h, args.hl_m, args.hl_kfinal, args.hl_seeds
+    flat = tuple(int(v) for v in args.hl_flat.split(","))
+    types = [(mo, q, Lt) for (mo, q) in (("ising", 2), ("potts", 10)) for Lt in (8, 12, 16, 20) if Lt < L]
+    t0 = time.perf_counter()
+    kws = [dict(model=mo, q=q, L=Lt, n_windows=4, m=32, kfinal=16, X=10000, seed=3000 + i)
+           for i, (mo, q, Lt) in enumerate(types)]
+    g, res = Wm.run_to_convergence(kws, args.max_seconds, log=log)
+    okr = [r["converged"] for r in res]
+    x, t = Wm.training_rows(g, kws, okr)
+    g.close()
+    t_data = time.perf_counter() - t0
+    net, info = Wm.train(x, t, steps=args.mlp_steps, batch=4096, lr=1e-3)
+    log(f"training: {sum(okr)}/{len(kws)} instances, {len(t)} rows, {t_data:.1f} s; network {info}")
+    target = dict(model="ising", q=2, L=L, n_windows=h, m=m, kfinal=kf, X=10000, flat=flat)
+    tab = Wm.warm_table(net, target)
+    k0 = args.k0 if args.k0 >= 0 else Wm.suggest_k0(info["rms"], L * L)
+    net.close()
+    ex = exact_ln_g(target)
+    ok = np.isfinite(ex)
+
+    def eps(lng):
+        e = np.abs(lng[ok] - ex[ok]) / np.abs(ex[ok])
+        return {"eps_max": float(e.max()), "eps_mean": float(e.mean()),
+                "abs_err_max": float(np.abs(lng[ok] - ex[ok]).max())}
+
+    groups = {}
+    for mode in ("plain", "warm"):
+        tk = [dict(target, seed=sd, k0=k0 if mode == "warm" else 0) for sd in range(1, n + 1)]
+        ts = time.perf_counter()
+        gg, rr = Wm.run_to_convergence(tk, args.max_seconds, warm_tables=[tab] * n if mode == "warm" else None,
+                                       poll=100, log=log)
+        wall = time.perf_counter() - ts
+        conv = all(r["converged"] for r in rr)
+        runs = []
+        for i, r in enumerate(rr):
+            row = dict(seed=i + 1, converged=r["converged"], intervals=r["intervals"], seconds=r["seconds"],
+                       min_k=r["min_k"])
+            if r["converged"]:
+                row.update(eps(gg.concat(i)[0]))
+            runs.append(row)
+        grp = dict(k0=k0 if mode == "warm" else 0, converged=conv, seconds=wall if conv else None,
+                   seconds_limit=None if conv else wall, runs=runs)
+        if conv:
+            mean_rows, _ = gg.ensemble(list(range(n)), R=0)
+            grp["n_run_mean"] = eps(mean_rows[0])
+            grp["gate_met"] = grp["n_run_mean"]["eps_max"] <= 5e-3
+        gg.close()
+        groups[mode] = grp
+        log(f"{mode}: converged {conv}, {wall:.0f} s, n-run mean {grp.get('n_run_mean')}")
+    out = {"mode": "headline: warm start vs plain REWL to 2^-%d" % kf,
+           "workload": f"Ising L={L} periodic, h={h}, m={m}, o=3/4, flatness {flat[0]}/{flat[1]}, X=1e4, "
+                       f"{n} seeds per group, ln f 1 (plain) or 2^-{k0} (warm) -> 2^-{kf}",
+           "train": {"types": types, "instances": len(kws), "converged": int(sum(okr)), "rows": int(len(t)),
+                     "seconds": t_data}, "network": info, "groups": groups}
+    if groups["plain"]["converged"] and groups["warm"]["converged"]:
+        out["speedup_warm_over_plain"] = groups["plain"]["seconds"] / groups["warm"]["seconds"]
+        out["speedup_with_training"] = groups["plain"]["seconds"] / (groups["warm"]["seconds"] + t_data
+                                                                      + info["seconds"])
+    return out
+
+
+def accuracy_study(rw, args) -> dict:
+    """Where the DOS error of Ising runs comes from (Sec. II.B joins against the pieces
+    themselves), judged against the exact DOS.  n seeds of one workload run in one
+    handle to ln f = 2^-kfinal.  Per run: the normalised error eps = |ln g^ - ln g| / ln g
+    (mean, max); per piece, its error r(E) = piece - exact over the levels that occur,
+    split into a constant (free: the joins remove it) and the rest; the change of r
+    between the piece's two join points (the joined DOS accumulates these changes from
+    the middle of the range to its ends); and the error of the same pieces joined by
+    the paper's rule after averaging the n runs' pieces window by window (Sec. II.B's
+    n-run mean), as rewl_ensemble does."""
+    L, h, m = args.acc_L, args.acc_h, args.acc_m
+    kw0 = dict(model="ising", q=2, L=L, n_windows=h, m=m, kfinal=args.acc_kfinal, X=10000)
+    if args.flat and args.flat_rule == "mean":
+        kw0["flat"] = tuple(int(v) for v in args.flat.split(","))
+    elif args.flat:
+        kw0.update(flat_rule=args.flat_rule, flat=tuple(int(v) for v in args.flat.split(",")))
+    if args.windows == "tilted":
+        kw0["windows"] = tilted_windows(rw, dict(kw0, seed=1))
+    seeds = list(range(1, args.acc_seeds + 1))
+    kws = [dict(kw0, seed=sd) for sd in seeds]
+    ex = exact_ln_g(kw0)
+    ok = np.isfinite(ex)
+    g = rw.Rewl([rw.make_config(**kw) for kw in kws], tune=rw.make_tune(poll_every=200))
+    t0 = time.perf_counter()
+    last = t0
+    done = False
+    while not done and time.perf_counter() - t0 < args.max_seconds:
+        done = g.run(200)
+        if time.perf_counter() - last > 20:
+            sts = [g.stats(i) for i in range(len(kws))]
+            print(f"[accuracy] {time.perf_counter() - t0:.0f} s: min k {[s['min_k'] for s in sts]}",
+                  file=sys.stderr, flush=True)
+            last = time.perf_counter()
+    secs = time.perf_counter() - t0
+    W, WB, lo, hi = rw.rewl_layout(rw.make_config(**kws[0]))
+
+    def eps(lng):
+        e = np.abs(lng[ok] - ex[ok]) / np.abs(ex[ok])
+        return float(e.mean()), float(e.max()), float(np.abs(lng[ok] - ex[ok]).max())
+
+    runs = []
+    for i in range(len(kws)):
+        st = g.stats(i)
+        pieces = g.pieces(i)
+        lng, join = g.concat(i)
+        pc = []
+        for a in range(h):
+            b = np.arange(lo[a], hi[a] + 1)
+            occ = ok[b]
+            r = pieces[a][: hi[a] - lo[a] + 1][occ] - ex[b][occ]
+            c = r.mean()
+            rr = np.full(b.size, np.nan)
+            rr[occ] = r - c
+            ends = [join[a - 1] if a > 0 else lo[a], join[a] if a < h - 1 else hi[a]]
+            drift = float(rr[ends[1] - lo[a]] - rr[ends[0] - lo[a]]) if np.all(np.isfinite(rr[[e - lo[a] for e in ends]])) else None
+            pc.append(dict(rms=float(np.sqrt(np.mean((r - c) ** 2))), max=float(np.abs(r - c).max()),
+                           drift_between_joins=drift))
+        e_mean, e_max, d_max = eps(lng)
+        d = lng - ex
+        runs.append(dict(seed=seeds[i], intervals=st["intervals"], min_k=st["min_k"], eps_mean=e_mean,
+                         eps_max=e_max, abs_err_max=d_max, err_E0=float(d[0]), err_Emax=float(d[W - 1]),
+                         err_low_end=[round(float(v), 4) for v in d[:24][ok[:24]]],
+                         err_high_end=[round(float(v), 4) for v in d[W - 24:][ok[W - 24:]]],
+                         joins=[int(j) for j in join], pieces=pc, round_trips=int(st["round_trips_total"])))
+    out = dict(mode="accuracy", workload=f"Ising L={L}, h={h}, m={m}, ln f -> 2^-{args.acc_kfinal}"
+               + (f", windows {args.windows}" if args.windows != "equal" else "")
+               + (f", flatness {kw0.get('flat_rule', 'mean')} {kw0.get('flat')}" if args.flat else ""),
+               seeds=seeds, converged=bool(done), seconds=secs, runs=runs)
+    if done:
+        mean_rows, _ = g.ensemble(list(range(len(kws))), R=0)
+        out["n_run_mean"] = dict(zip(("eps_mean", "eps_max", "abs_err_max"), eps(mean_rows[0])))
+        d = mean_rows[0] - ex
+        out["n_run_mean"].update(err_E0=float(d[0]), err_Emax=float(d[W - 1]),
+                                 err_low_end=[round(float(v), 4) for v in d[:24][ok[:24]]],
+                                 err_high_end=[round(float(v), 4) for v in d[W - 24:][ok[W - 24:]]])
+    g.close()
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -535,6 +692,21 @@ def main(argv=None):
     ap.add_argument("--study-L", type=int, default=24)
     ap.add_argument("--study-kfinal", type=int, default=14)
     ap.add_argument("--study-seeds", type=int, default=4)
+    ap.add_argument("--headline", action="store_true",
+                    help="warm start vs plain to 2^-kfinal on an Ising target with the DOS error gate")
+    ap.add_argument("--hl-L", type=int, default=24)
+    ap.add_argument("--hl-h", type=int, default=8)
+    ap.add_argument("--hl-m", type=int, default=64)
+    ap.add_argument("--hl-kfinal", type=int, default=27)
+    ap.add_argument("--hl-seeds", type=int, default=8)
+    ap.add_argument("--hl-flat", default="19,20")
+    ap.add_argument("--accuracy-study", action="store_true",
+                    help="split the DOS error of Ising runs into piece shape and join parts (exact DOS)")
+    ap.add_argument("--acc-L", type=int, default=32)
+    ap.add_argument("--acc-h", type=int, default=8)
+    ap.add_argument("--acc-m", type=int, default=16)
+    ap.add_argument("--acc-kfinal", type=int, default=20)
+    ap.add_argument("--acc-seeds", type=int, default=4)
     ap.add_argument("--ensemble-study", action="store_true",
                     help="the paper's Potts L=100 workload as n runs + bootstrap + specific heat")
     ap.add_argument("--ens-runs", type=int, default=4)
@@ -594,6 +766,12 @@ def main(argv=None):
     if args.ensemble_study:
         print(json.dumps(ensemble_study(rw, args)), flush=True)
         return 0
+    if args.accuracy_study:
+        print(json.dumps(accuracy_study(rw, args)), flush=True)
+        return 0
+    if args.headline:
+        print(json.dumps(headline_study(rw, args)), flush=True)
+        return 0
     if args.balanced_study:
         print(json.dumps(balanced_study(rw, args)), flush=True)
         return 0
@@ -620,7 +798,10 @@ def main(argv=None):
     S = sum(kw["n_windows"] * kw["m"] for kw in kws)
     att_step = sum(kw["n_windows"] * kw["m"] * kw["X"] for kw in kws)
     t_create = time.perf_counter()
-    tune = rw.make_tune(args.sweep, args.wpb, 0, 1 << 20, lds_target_kb=args.lds_kb,
+    # the timed steps replay the interval's captured HIP graph (no host work between
+    # intervals); the kernel times come from a second pass of the same length with
+    # per-launch events, which synchronises the host once per interval
+    tune = rw.make_tune(args.sweep, args.wpb, 1, 1 << 20, lds_target_kb=args.lds_kb,
                         autotune=1 if args.autotune else 0)
     g = rw.Rewl(cfgs, tune=tune)
     t_create = time.perf_counter() - t_create
@@ -629,13 +810,14 @@ def main(argv=None):
           f"LDS {info['lds_bytes']} B, tune {g.tune()}, create {t_create:.2f} s", file=sys.stderr, flush=True)
 
     rw.rewl_run_exact(g.h, args.warmup)
-    rw.rewl_set_timing(g.h, True)
-    st0 = g.stats()
     _sync()
     t0 = time.perf_counter()
     rw.rewl_run_exact(g.h, args.steps)
     _sync()
     dt = time.perf_counter() - t0
+    rw.rewl_set_timing(g.h, True)
+    st0 = g.stats()
+    rw.rewl_run_exact(g.h, args.steps)
     st1 = g.stats()
     rw.rewl_set_timing(g.h, False)
     attempts = args.steps * att_step
@@ -663,7 +845,7 @@ def main(argv=None):
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": label, "walkers": S, "attempts_per_step": att_step,
+        "config": {"workload": label, "walkers": S, "attempts_per_step": att_step, "graph": True,
                    "sweep": info["sweep_kind"], "walkers_per_block": info["walkers_per_block"]},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
                      "unit": "Tops/s", "frac": achieved / PEAK_LANE_OPS,
@@ -689,14 +871,16 @@ def batch_line(rw, steps: int = 10, warmup: int = 2) -> dict:
     """The 64-instance batch, autotuned, timed like the main workload (extra keys)."""
     kws = workload("batch64")
     t0 = time.perf_counter()
-    g = rw.Rewl([rw.make_config(**kw) for kw in kws], tune=rw.make_tune(autotune=1, poll_every=1 << 20))
+    g = rw.Rewl([rw.make_config(**kw) for kw in kws],
+                tune=rw.make_tune(autotune=1, use_graph=1, poll_every=1 << 20))
     t_create = time.perf_counter() - t0
     rw.rewl_run_exact(g.h, warmup)
+    t0 = time.perf_counter()
+    rw.rewl_run_exact(g.h, steps)                  # graph replays
+    dt = time.perf_counter() - t0
     rw.rewl_set_timing(g.h, True)
     st0 = g.stats()
-    t0 = time.perf_counter()
-    rw.rewl_run_exact(g.h, steps)
-    dt = time.perf_counter() - t0
+    rw.rewl_run_exact(g.h, steps)                  # per-launch events
     st1 = g.stats()
     att = steps * sum(kw["n_windows"] * kw["m"] * kw["X"] for kw in kws)
     ops = steps * sum(OPS_PER_ATTEMPT[kw["model"]] * kw["n_windows"] * kw["m"] * kw["X"] for kw in kws)
@@ -707,7 +891,7 @@ def batch_line(rw, steps: int = 10, warmup: int = 2) -> dict:
     print(f"[bench] batch64: {att / dt:.4g} attempts/s, sweep {sweep_ms:.3f} ms/launch, interval "
           f"{interval_ms:.3f} ms, tune {tune}, create+autotune {t_create:.2f} s", file=sys.stderr, flush=True)
     return {"workload": LABELS["batch64"], "attempts_per_s": att / dt, "ms_per_step": dt * 1e3 / steps,
-            "steps": steps, "sweep_ms": sweep_ms, "interval_ms": interval_ms,
+            "steps": steps, "sweep_ms": sweep_ms, "interval_ms": interval_ms, "graph": bool(tune["use_graph"]),
             "sweep": info["sweep_kind"], "lds_target_kb": tune["lds_target_kb"],
             "roofline": {"bound": "alu", "achieved": ops / steps / (sweep_ms * 1e-3) / 1e12,
                          "peak": PEAK_LANE_OPS / 1e12, "unit": "Tops/s",

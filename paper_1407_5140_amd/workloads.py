@@ -16,7 +16,8 @@ def single(name: str) -> dict:
     Ising L=32 (8 windows x 16 walkers, ln f to 2^-20), 10-state Potts L=100 (the paper's
     77 windows of 1001 bins, 8 walkers each),
     Ising L=64 (16 windows x 64 walkers) and 10-state Potts L=32 (32 windows x 128
-    walkers), both to ln f = 2^-27; 75% overlap, flatness 4/5, X = 10^4, seed 1."""
+    walkers), both to ln f = 2^-27, and the larger targets Ising L=128 (32 x 64) and 10-state
+    Potts L=64 (32 x 128); 75% overlap, flatness 4/5, X = 10^4, seed 1."""
     table = {
         "ising8": dict(model="ising", q=2, L=8, n_windows=4, m=1, kfinal=20, X=10000, seed=1),
         "ising32": dict(model="ising", q=2, L=32, n_windows=8, m=16, kfinal=20, X=10000, seed=1),
@@ -24,6 +25,10 @@ def single(name: str) -> dict:
         "potts32": dict(model="potts", q=10, L=32, n_windows=32, m=128, kfinal=27, X=10000, seed=1),
         # the paper's smallest Potts lattice (Sec. IV.A): 77 windows of 1001 bins, 75 % overlap
         "potts100": dict(model="potts", q=10, L=100, n_windows=77, m=8, kfinal=27, X=10000, seed=1),
+        # the warm start's larger targets: Ising L=128 (h=32, m=64) and 10-state Potts L=64
+        # (h=32, m=128), both to ln f = 2^-27
+        "ising128": dict(model="ising", q=2, L=128, n_windows=32, m=64, kfinal=27, X=10000, seed=1),
+        "potts64": dict(model="potts", q=10, L=64, n_windows=32, m=128, kfinal=27, X=10000, seed=1),
     }
     return dict(table[name])
 
