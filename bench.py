@@ -666,6 +666,8 @@ def main(argv=None):
                     help="only copy a device buffer of this size and exit (a kernel of known "
                          "traffic for scaling the HBM byte counters)")
     ap.add_argument("--wpb", type=int, default=0, help="walkers per block (0 = library choice)")
+    ap.add_argument("--placement", default="auto", choices=["auto", "lds", "device"],
+                    help="wave sweep: where the walkers' counts live while it runs")
     ap.add_argument("--lds-kb", type=int, default=0,
                     help="lane sweep: cap on a tile's LDS in KiB (0 = the device limit)")
     ap.add_argument("--flat-rule", default="mean", choices=["mean", "visits"],
@@ -778,7 +780,7 @@ def main(argv=None):
     kws = workload(args.workload)
     label = LABELS[args.workload]
     if args.converge:
-        tune = rw.make_tune(args.sweep, args.wpb, 1, 200)
+        tune = rw.make_tune(args.sweep, args.wpb, 1, 200, table_placement=args.placement)
         kw = dict(kws[0], flat_rule=args.flat_rule)
         if args.flat:
             kw["flat"] = tuple(int(v) for v in args.flat.split(","))
@@ -802,11 +804,12 @@ def main(argv=None):
     # intervals); the kernel times come from a second pass of the same length with
     # per-launch events, which synchronises the host once per interval
     tune = rw.make_tune(args.sweep, args.wpb, 1, 1 << 20, lds_target_kb=args.lds_kb,
-                        autotune=1 if args.autotune else 0)
+                        autotune=1 if args.autotune else 0, table_placement=args.placement)
     g = rw.Rewl(cfgs, tune=tune)
     t_create = time.perf_counter() - t_create
     info = g.info()
-    print(f"[bench] {label}: {S} walkers, {info['sweep_kind']} sweep, walkers/block {info['walkers_per_block']}, "
+    print(f"[bench] {label}: {S} walkers, {info['sweep_kind']} sweep ({info['table_placement']} counts), "
+          f"walkers/block {info['walkers_per_block']}, "
           f"LDS {info['lds_bytes']} B, tune {g.tune()}, create {t_create:.2f} s", file=sys.stderr, flush=True)
 
     rw.rewl_run_exact(g.h, args.warmup)
@@ -846,7 +849,8 @@ def main(argv=None):
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": label, "walkers": S, "attempts_per_step": att_step, "graph": True,
-                   "sweep": info["sweep_kind"], "walkers_per_block": info["walkers_per_block"]},
+                   "sweep": info["sweep_kind"], "walkers_per_block": info["walkers_per_block"],
+                   "table_placement": info["table_placement"]},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
                      "unit": "Tops/s", "frac": achieved / PEAK_LANE_OPS,
                      "traffic": None if traffic is None else sum(traffic),

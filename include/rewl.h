@@ -92,6 +92,15 @@ enum { REWL_FLAT_MEAN = 0, REWL_FLAT_VISITS = 1 };
  * walkers in all, LANE above that.  Both give bit-identical results.            */
 enum { REWL_SWEEP_AUTO = 0, REWL_SWEEP_LANE = 1, REWL_SWEEP_WAVE = 2 };
 
+/* Where the WAVE sweep keeps a walker's counts while it runs.  LDS: a 32-bit copy
+ * beside the walker's site map and lattice.  DEVICE: the 64-bit counts in device
+ * memory, read when the walker's 64-bin register window of ln g is loaded and
+ * written when it moves (a few times per thousand attempts), so LDS holds only the
+ * window's base table, the site maps and the lattices, and more walkers fit a
+ * block on large lattices.  AUTO: DEVICE where it fits more walkers per block,
+ * else LDS.  Both give bit-identical results; the LANE sweep always uses LDS.    */
+enum { REWL_TABLE_AUTO = 0, REWL_TABLE_LDS = 1, REWL_TABLE_DEVICE = 2 };
+
 /* Optional tuning of a batch (NULL = library choice). */
 typedef struct {
     int32_t walkers_per_block;  /* LANE: walkers per LDS tile (power of two <= 64);
@@ -101,13 +110,20 @@ typedef struct {
     int32_t sweep_kind;         /* REWL_SWEEP_*, applied to every instance that allows it */
     int32_t lds_target_kb;      /* LANE: cap on a tile's LDS (sets walkers per block and
                                    so blocks per CU); 0 = the device limit               */
-    int32_t autotune;           /* 1: time candidate variants / LDS targets on the real
-                                   batch for two intervals at creation, keep the fastest */
+    int32_t autotune;           /* 1: time candidate variants, LDS targets, the
+                                   persistent lane sweep and table placements on the
+                                   real batch for two intervals at creation, keep the
+                                   fastest                                               */
     int32_t guard_band_log2;    /* guard band of the fast acceptance test, 2^v:
                                    0 = 2^-40 (the default); -40..-2 widen it.  Every
                                    decision stays exact either way; a wider band only
                                    sends more of them to the exact slow path (used by
                                    the tests to exercise that path).                  */
+    int32_t table_placement;    /* REWL_TABLE_* (WAVE sweep)                             */
+    int32_t persistent;         /* LANE sweep: 1 = a grid of as many blocks as the GPU
+                                   holds at once, each taking tiles (longest first) from
+                                   a device-side queue until none is left; 0 = one
+                                   block per tile, handed out by the hardware          */
 } rewl_tune;
 
 typedef struct rewl_handle rewl_handle;
@@ -281,9 +297,10 @@ const char* rewl_last_error(void);
 rewl_status rewl_get_tune(rewl_handle* h, rewl_tune* out);
 
 /* Number of instances, and for one instance the sweep variant chosen
- * (REWL_SWEEP_LANE / _WAVE), walkers per block and LDS bytes per block.       */
+ * (REWL_SWEEP_LANE / _WAVE), walkers per block, LDS bytes per block and the
+ * count table's placement (REWL_TABLE_LDS / _DEVICE).  Any pointer may be NULL. */
 rewl_status rewl_info(rewl_handle* h, int32_t instance, int32_t* n_instances, int32_t* sweep_kind,
-                      int32_t* walkers_per_block, size_t* lds_bytes);
+                      int32_t* walkers_per_block, size_t* lds_bytes, int32_t* table_placement);
 
 /* Diagnostics (run on the device, used by the tests):
  * the full acceptance predicate u53 < 2^53 exp(delta) for n pairs: out[i] =

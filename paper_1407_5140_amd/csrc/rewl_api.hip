@@ -138,7 +138,7 @@ rewl_status validate(const rewl_config& c)
 
 struct HostInst {
     rewl_config cfg;
-    int N, W, h, m, S, WB, log2m, wpr, wpb, kind;
+    int N, W, h, m, S, WB, log2m, wpr, wpb, kind, placement;
     size_t lds;
     std::vector<int32_t> lo, hi, nreach;
     std::vector<uint8_t> mask;
@@ -157,6 +157,8 @@ struct rewl_handle {
     Inst* d_insts = nullptr;
     Tile* d_tiles = nullptr;
     int ntiles = 0;
+    int32_t* d_queue = nullptr; // tile queue of the persistent lane sweep
+    int persist_grid = 0;       // its blocks: as many as the GPU holds at once
     Tile* d_wtiles = nullptr;
     int nwtiles = 0;
     int wave_threads = 64;
@@ -201,7 +203,10 @@ rewl_status enqueue_interval(rewl_handle* H, bool time_it)
         hipLaunchKernelGGL(k_rng, dim3(H->rng_grid), dim3(256), 0, H->stream, H->d_insts,
                            H->d_rng_start, H->n);
     if (time_it) HIP_TRY(hipEventRecord(H->ev[1], H->stream));
-    if (H->ntiles > 0)
+    if (H->ntiles > 0 && H->tune.persistent)
+        hipLaunchKernelGGL(k_sweep_persist, dim3(H->persist_grid), dim3(64), H->max_lds, H->stream, H->d_insts,
+                           H->d_tiles, H->ntiles, H->d_queue);
+    else if (H->ntiles > 0)
         hipLaunchKernelGGL(k_sweep, dim3(H->ntiles), dim3(64), H->max_lds, H->stream, H->d_insts,
                            H->d_tiles, H->ntiles);
     if (H->nwtiles > 0)
@@ -212,7 +217,8 @@ rewl_status enqueue_interval(rewl_handle* H, bool time_it)
     if (H->exch_threads > 0)
         hipLaunchKernelGGL(k_exchange, dim3((H->exch_threads + 3) / 4), dim3(256), 0, H->stream,
                            H->d_insts, H->d_exch_start, H->n);
-    hipLaunchKernelGGL(k_advance, dim3((H->n + 63) / 64), dim3(64), 0, H->stream, H->d_insts, H->n);
+    hipLaunchKernelGGL(k_advance, dim3((H->n + 63) / 64), dim3(64), 0, H->stream, H->d_insts, H->n,
+                       H->d_queue);
     if (time_it) HIP_TRY(hipEventRecord(H->ev[3], H->stream));
     HIP_TRY(hipGetLastError());
     return REWL_OK;
@@ -456,6 +462,10 @@ static rewl_status create_impl(const rewl_config* cfgs, int32_t n, void* hip_str
 
     if (tune && tune->guard_band_log2 != 0 && (tune->guard_band_log2 < -40 || tune->guard_band_log2 > -2))
         return fail(REWL_E_INVALID, "guard_band_log2 must be 0 (2^-40) or in [-40, -2]");
+    if (tune && (tune->table_placement < REWL_TABLE_AUTO || tune->table_placement > REWL_TABLE_DEVICE))
+        return fail(REWL_E_INVALID, "table_placement must be REWL_TABLE_AUTO, _LDS or _DEVICE");
+    if (tune && tune->persistent != 0 && tune->persistent != 1)
+        return fail(REWL_E_INVALID, "persistent must be 0 or 1");
     rewl_handle* H = new rewl_handle();
     H->device = dev;
     if (tune) H->tune = *tune;
@@ -507,13 +517,14 @@ static rewl_status create_impl(const rewl_config* cfgs, int32_t n, void* hip_str
         // 3.50 ms per 10^4 attempts); with tens of thousands of walkers the lane
         // variant's width wins (the 64-instance batch).
         // any lattice, as long as one walker's wave tables fit (the site map is bounded)
-        const bool wave_ok = wave_lds_bytes(c.model, c.L, hi.WB, 1) <= (size_t)lds_limit;
+        const bool wave_ok = wave_lds_bytes(c.model, c.L, hi.WB, 1, true) <= (size_t)lds_limit;
         int64_t total_walkers = 0;
         for (int u = 0; u < n; ++u) total_walkers += (int64_t)cfgs[u].n_windows * cfgs[u].walkers_per_window;
         hi.kind = REWL_SWEEP_LANE;
         if (wave_ok && (H->tune.sweep_kind == REWL_SWEEP_WAVE ||
                         (H->tune.sweep_kind == REWL_SWEEP_AUTO && total_walkers <= 8192)))
             hi.kind = REWL_SWEEP_WAVE;
+        hi.placement = REWL_TABLE_LDS;
         if (hi.kind == REWL_SWEEP_LANE) {
             int want = H->tune.walkers_per_block > 0 ? H->tune.walkers_per_block : 64;
             int wpb = 1;
@@ -526,11 +537,23 @@ static rewl_status create_impl(const rewl_config* cfgs, int32_t n, void* hip_str
             H->max_lds = std::max(H->max_lds, hi.lds);
         } else {
             int want = H->tune.walkers_per_block > 0 ? H->tune.walkers_per_block : 4;
-            int G = 1;
-            while (G * 2 <= std::min(want, std::min(8, hi.m))) G *= 2;
-            while (G > 1 && wave_lds_bytes(c.model, c.L, hi.WB, G) > (size_t)lds_limit) G /= 2;
+            int G0 = 1;
+            while (G0 * 2 <= std::min(want, std::min(8, hi.m))) G0 *= 2;
+            // walkers per block that fit with the counts in LDS and in device memory
+            auto fit = [&](bool hg) {
+                int G = G0;
+                while (G > 1 && wave_lds_bytes(c.model, c.L, hi.WB, G, hg) > (size_t)lds_limit) G /= 2;
+                return wave_lds_bytes(c.model, c.L, hi.WB, G, hg) <= (size_t)lds_limit ? G : 0;
+            };
+            const int g_lds = fit(false), g_glob = fit(true);
+            bool hg;
+            if (H->tune.table_placement == REWL_TABLE_LDS && g_lds > 0) hg = false;
+            else if (H->tune.table_placement == REWL_TABLE_DEVICE) hg = true;
+            else hg = g_glob > g_lds;          // auto: device memory only where it fits more walkers
+            const int G = hg ? g_glob : g_lds;
+            hi.placement = hg ? REWL_TABLE_DEVICE : REWL_TABLE_LDS;
             hi.wpb = G;
-            hi.lds = wave_lds_bytes(c.model, c.L, hi.WB, G);
+            hi.lds = wave_lds_bytes(c.model, c.L, hi.WB, G, hg);
             H->max_lds_wave = std::max(H->max_lds_wave, hi.lds);
             H->wave_threads = std::max(H->wave_threads, 64 * G);
         }
@@ -544,6 +567,7 @@ static rewl_status create_impl(const rewl_config* cfgs, int32_t n, void* hip_str
         d.flat_den = c.flat_den; d.flat_rule = c.flat_rule; d.kfinal = c.lnf_kfinal; d.exch = c.exchange_enabled; d.wpr = hi.wpr;
         d.X = c.exchange_interval; d.k0 = (uint32_t)c.seed; d.k1 = (uint32_t)(c.seed >> 32);
         d.band = band;
+        d.hglobal = hi.placement == REWL_TABLE_DEVICE ? 1 : 0;
         d.XP = (c.exchange_interval + 31) / 32 * 32;   // two draw chunks of 16
         if ((uint64_t)d.XP * hi.S >= (uint64_t(1) << 32))
             return bail(fail(REWL_E_INVALID, "instance " + std::to_string(i) + ": walkers x interval exceeds 2^32 draws"));
@@ -616,6 +640,9 @@ static rewl_status create_impl(const rewl_config* cfgs, int32_t n, void* hip_str
     }
     rewl_status s = H->alloc(&H->d_ctr, n);
     if (s != REWL_OK) return bail(s);
+    if ((s = H->alloc(&H->d_queue, 1)) != REWL_OK) return bail(s);
+    if (hipMemsetAsync(H->d_queue, 0, 4, H->stream) != hipSuccess)
+        return bail(fail(REWL_E_DEVICE, "memset failed"));
     if (hipHostMalloc((void**)&H->h_ctr, sizeof(InstCtr) * n, hipHostMallocDefault) != hipSuccess)
         return bail(fail(REWL_E_NOMEM, "hipHostMalloc failed"));
     if (hipMemsetAsync(H->d_ctr, 0, sizeof(InstCtr) * n, H->stream) != hipSuccess)
@@ -624,6 +651,13 @@ static rewl_status create_impl(const rewl_config* cfgs, int32_t n, void* hip_str
         H->inst[i].dev.ctr = H->d_ctr + i;
         devs[i] = H->inst[i].dev;
     }
+    // lane tiles longest first (Potts before Ising, larger lattices first): the
+    // persistent sweep hands them out in this order, the plain launch in block order
+    std::stable_sort(tiles.begin(), tiles.end(), [&](const Tile& x, const Tile& y) {
+        const HostInst &a = H->inst[x.inst], &b = H->inst[y.inst];
+        if (a.cfg.model != b.cfg.model) return a.cfg.model > b.cfg.model;
+        return a.N > b.N;
+    });
     H->ntiles = (int)tiles.size();
     H->nwtiles = (int)wtiles.size();
     H->nmerge = (int)merges.size();
@@ -652,10 +686,20 @@ static rewl_status create_impl(const rewl_config* cfgs, int32_t n, void* hip_str
     if (!ok) return bail(fail(REWL_E_DEVICE, "descriptor upload failed"));
     if (hipFuncSetAttribute((const void*)k_sweep, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)std::max<size_t>(H->max_lds, 1)) != hipSuccess ||
+        hipFuncSetAttribute((const void*)k_sweep_persist, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)std::max<size_t>(H->max_lds, 1)) != hipSuccess ||
         hipFuncSetAttribute((const void*)k_sweep_wave, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)std::max<size_t>(H->max_lds_wave, 1)) != hipSuccess)
         return bail(fail(REWL_E_DEVICE, "cannot raise the dynamic LDS limit"));
 
+    if (H->ntiles > 0) {
+        int per_cu = 0, n_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_sweep_persist, 64,
+                                                         std::max<size_t>(H->max_lds, 1)) != hipSuccess ||
+            hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            return bail(fail(REWL_E_DEVICE, "occupancy query failed"));
+        H->persist_grid = std::max(1, std::min(H->ntiles, std::max(per_cu, 1) * std::max(n_cu, 1)));
+    }
     hipLaunchKernelGGL(k_init, dim3((H->slot_threads + 127) / 128), dim3(128), 0, st, H->d_insts,
                        H->d_slot_start, n);
     if (hipGetLastError() != hipSuccess) return bail(fail(REWL_E_DEVICE, "init launch failed"));
@@ -673,23 +717,29 @@ static rewl_status autotune(const rewl_config* cfgs, int32_t n, void* hip_stream
 {
     std::vector<rewl_tune> cand;
     const bool all_wave = true;         // the wave variant runs every supported lattice
-    for (int kb : {40, 53, 80, 0}) {
-        rewl_tune t = base;
-        t.sweep_kind = REWL_SWEEP_LANE;
-        t.walkers_per_block = 0;
-        t.lds_target_kb = kb;
-        t.autotune = 0;
-        cand.push_back(t);
-    }
-    if (all_wave)
-        for (int g : {1, 4}) {
+    for (int kb : {40, 53, 80, 0})
+        for (int persist : {0, 1}) {
             rewl_tune t = base;
-            t.sweep_kind = REWL_SWEEP_WAVE;
-            t.walkers_per_block = g;
-            t.lds_target_kb = 0;
+            t.table_placement = REWL_TABLE_AUTO;
+            t.sweep_kind = REWL_SWEEP_LANE;
+            t.walkers_per_block = 0;
+            t.lds_target_kb = kb;
+            t.persistent = persist;
             t.autotune = 0;
             cand.push_back(t);
         }
+    if (all_wave)
+        for (int g : {1, 4})
+            for (int pl : {REWL_TABLE_LDS, REWL_TABLE_DEVICE}) {
+                rewl_tune t = base;
+                t.sweep_kind = REWL_SWEEP_WAVE;
+                t.walkers_per_block = g;
+                t.lds_target_kb = 0;
+                t.persistent = 0;
+                t.table_placement = pl;
+                t.autotune = 0;
+                cand.push_back(t);
+            }
     double best_ms = 1e300;
     *best = cand[0];
     for (const rewl_tune& t : cand) {
@@ -795,7 +845,7 @@ rewl_status rewl_set_timing(rewl_handle* H, int32_t on)
 }
 
 rewl_status rewl_info(rewl_handle* H, int32_t i, int32_t* n_instances, int32_t* kind, int32_t* wpb,
-                      size_t* lds)
+                      size_t* lds, int32_t* placement)
 {
     rewl_status s = check_inst(H, i);
     if (s != REWL_OK) return s;
@@ -803,6 +853,7 @@ rewl_status rewl_info(rewl_handle* H, int32_t i, int32_t* n_instances, int32_t* 
     if (kind) *kind = H->inst[i].kind;
     if (wpb) *wpb = H->inst[i].wpb;
     if (lds) *lds = H->inst[i].lds;
+    if (placement) *placement = H->inst[i].placement;
     return REWL_OK;
 }
 

@@ -207,6 +207,8 @@ struct Inst {
                         //     window 0, 2 reached window h-1 since
     int32_t* rt_count;  // [S] per replica: completed round trips 0 -> h-1 -> 0
     double band;        // guard band of the fast acceptance test
+    int32_t hglobal;    // wave sweep: counts read from device memory, not an LDS copy
+    int32_t pad_;
     InstCtr* ctr;
 };
 

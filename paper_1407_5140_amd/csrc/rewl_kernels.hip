@@ -348,11 +348,8 @@ __device__ void sweep_tile(const Inst& I, const Tile& tile, char* smem)
     }
 }
 
-__global__ void __launch_bounds__(64) k_sweep(const Inst* __restrict__ insts,
-                                              const Tile* __restrict__ tiles, int ntiles)
+__device__ __forceinline__ void sweep_one_tile(const Inst* __restrict__ insts, const Tile& tile, char* smem)
 {
-    extern __shared__ __align__(16) char smem[];
-    const Tile tile = tiles[blockIdx.x];
     const Inst& I = insts[tile.inst];
     if (I.ctr->all_done) return;
     if (I.model == 0) {
@@ -360,6 +357,34 @@ __global__ void __launch_bounds__(64) k_sweep(const Inst* __restrict__ insts,
         else sweep_tile<0, 2>(I, tile, smem);
     } else {
         sweep_tile<1, 1>(I, tile, smem);
+    }
+}
+
+__global__ void __launch_bounds__(64) k_sweep(const Inst* __restrict__ insts,
+                                              const Tile* __restrict__ tiles, int ntiles)
+{
+    extern __shared__ __align__(16) char smem[];
+    sweep_one_tile(insts, tiles[blockIdx.x], smem);
+}
+
+// Persistent form: a grid sized to the blocks the GPU holds at once; each block
+// takes the next tile from a queue counter until the tiles run out (the tiles
+// are ordered longest-first by the host).  The counter is reset by k_advance at
+// the end of the interval, so the launch sequence needs no memset.
+__global__ void __launch_bounds__(64) k_sweep_persist(const Inst* __restrict__ insts,
+                                                      const Tile* __restrict__ tiles, int ntiles,
+                                                      int32_t* __restrict__ queue)
+{
+    extern __shared__ __align__(16) char smem[];
+    __shared__ int next;
+    for (;;) {
+        if (threadIdx.x == 0) next = atomicAdd(queue, 1);
+        __syncthreads();
+        const int t = next;
+        __syncthreads();
+        if (t >= ntiles) break;             // block-uniform: every wave of the grid ends here
+        sweep_one_tile(insts, tiles[t], smem);
+        __syncthreads();                    // the tile's LDS is free before the next one is staged
     }
 }
 
@@ -378,10 +403,10 @@ __global__ void __launch_bounds__(64) k_sweep(const Inst* __restrict__ insts,
 // only adds attempts to the out-of-date sets, never removes one.
 constexpr int kWaveMapMax = 4096;
 __host__ __device__ inline int wave_map_entries(int N) { return N < kWaveMapMax ? N : kWaveMapMax; }
-__host__ __device__ inline size_t wave_lds_bytes(int model, int L, int WB, int G)
+__host__ __device__ inline size_t wave_lds_bytes(int model, int L, int WB, int G, bool hglobal = false)
 {
     const size_t nb = (size_t)WB + 2 * kPad, N = (size_t)L * L;
-    size_t s = nb * 8 + (size_t)G * nb * 4;
+    size_t s = nb * 8 + (hglobal ? 0 : (size_t)G * nb * 4);
     s = (s + 7) & ~size_t(7);
     s += (size_t)G * wave_map_entries((int)N) * 8;
     s += model == 1 ? (size_t)G * N : (size_t)G * L * ((L + 63) / 64) * 8;
@@ -433,7 +458,12 @@ __device__ __forceinline__ int ising_d_words(const uint64_t* rows, int wpr, int 
 //   or before the first attempt that a flip of the run made out of date.
 // WIDE: N > 4096 (site map entries shared mod 4096; Ising rows of several
 // words).  The narrow form keeps the one-word rows and the direct map.
-template <int MODEL, bool WIDE>
+// HG: the walker's counts stay in device memory (the 64-bit H array) instead of
+// an LDS copy: they are touched only when the register window is loaded or
+// stored and by the flatness test, so LDS then holds only the window's base table,
+// the site maps and the lattices, and more walkers fit a block.  Both placements
+// compute identical results.
+template <int MODEL, bool WIDE, bool HG>
 __device__ void sweep_wave(const Inst& I, const Tile& tile, char* smem)
 {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -450,10 +480,11 @@ __device__ void sweep_wave(const Inst& I, const Tile& tile, char* smem)
     }
     const bool active = wave < G;
     const int r = tile.r0 + wave, slot = a * I.m + r;
-    uint32_t* lH = (uint32_t*)(lbase + nbins) + (size_t)wave * nbins;
+    uint32_t* lH = (uint32_t*)(lbase + nbins) + (size_t)wave * nbins;           // LDS placement only
+    uint64_t* gH = I.H + (size_t)slot * WB;                                      // the walker's counts
     const int M = WIDE ? kWaveMapMax : N;
     const int wpr = WIDE ? I.wpr : 1;                         // Ising words per row
-    const size_t off_map = ((size_t)nbins * 8 + (size_t)G * nbins * 4 + 7) & ~size_t(7);
+    const size_t off_map = ((size_t)nbins * 8 + (HG ? 0 : (size_t)G * nbins * 4) + 7) & ~size_t(7);
     uint64_t* lmap = (uint64_t*)(smem + off_map) + (size_t)wave * M;
     uint8_t* llat = (uint8_t*)(smem + off_map + (size_t)G * M * 8) + (size_t)wave * N;
     uint64_t* lrow = (uint64_t*)(smem + off_map + (size_t)G * M * 8) + (size_t)wave * L * wpr;
@@ -462,7 +493,7 @@ __device__ void sweep_wave(const Inst& I, const Tile& tile, char* smem)
     // the walker's counts relative to an offset of its own (a per-walker constant
     // cancels from every decision), chosen and checked as in sweep_tile
     uint64_t cw = 0;
-    if (active) {
+    if (active && !HG) {
         const uint64_t hc0 = I.H[(size_t)slot * WB + (I.bin[slot] - lo)];
         cw = hc0 > (1ull << 31) ? hc0 - (1ull << 31) : 0ull;
         const uint64_t span = 0xffffffffull - (uint64_t)I.X;
@@ -481,6 +512,8 @@ __device__ void sweep_wave(const Inst& I, const Tile& tile, char* smem)
             lH[i] = hv;
         }
         if (bad) atomicOr(&I.ctr->err, kErrOverflow);
+    }
+    if (active) {
         for (int i = lane; i < M; i += 64) lmap[i] = 0;
         if (MODEL == 0) {
             for (int i = lane; i < L * wpr; i += 64) lrow[i] = I.lat[(size_t)slot * L * wpr + i];
@@ -510,15 +543,28 @@ __device__ void sweep_wave(const Inst& I, const Tile& tile, char* smem)
     int idx = b - b0;                     // the walker's bin, as a lane of the window
     const double unscale = __builtin_ldexp(1.0, k);
     double gl;
+    // with HG the table entries are absolute counts (below 2^53: exact in FP64)
+    auto occurs = [&](int i) { return i >= kPad && i < kPad + width && I.mask[lo + i - kPad]; };
     auto load_window = [&]() {
         const int i = b0 + lane;
-        gl = i < nbins ? __builtin_fma((double)lH[i], scale, lbase[i]) : __builtin_inf();
+        if (HG) {
+            // the window's entries may have been stored by other lanes of this wave
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            gl = i < nbins ? (occurs(i) ? __builtin_fma((double)gH[i - kPad], scale, lbase[i]) : lbase[i])
+                           : __builtin_inf();
+        } else {
+            gl = i < nbins ? __builtin_fma((double)lH[i], scale, lbase[i]) : __builtin_inf();
+        }
     };
     auto store_window = [&]() {
         const int i = b0 + lane;
         // pads and levels that do not occur are never visited: leave them
-        if (i >= kPad && i < kPad + WB && lH[i] != 0xffffffffu)
+        if (HG) {
+            if (occurs(i)) gH[i - kPad] = (uint64_t)((gl - lbase[i]) * unscale);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        } else if (i >= kPad && i < kPad + WB && lH[i] != 0xffffffffu) {
             lH[i] = (uint32_t)((gl - lbase[i]) * unscale);
+        }
     };
     load_window();
     // B + j incv is the walker's ln g at its current bin before attempt j of the
@@ -664,11 +710,14 @@ __device__ void sweep_wave(const Inst& I, const Tile& tile, char* smem)
     if (lane == idx) gl = B;
     store_window();
 
-    // ---- write back
-    for (int i = lane; i < WB; i += 64) {
-        const uint32_t hv = lH[i + kPad];
-        I.H[(size_t)slot * WB + i] = hv == 0xffffffffu ? 0ull : (uint64_t)hv + cw;
-    }
+    // ---- write back (HG: the window's store above is the write back)
+    if (!HG)
+        for (int i = lane; i < WB; i += 64) {
+            const uint32_t hv = lH[i + kPad];
+            gH[i] = hv == 0xffffffffu ? 0ull : (uint64_t)hv + cw;
+        }
+    else
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     if (MODEL == 0) {
         for (int i = lane; i < L * wpr; i += 64) I.lat[(size_t)slot * L * wpr + i] = lrow[i];
     } else {
@@ -680,28 +729,30 @@ __device__ void sweep_wave(const Inst& I, const Tile& tile, char* smem)
     }
     // ---- flatness (Sec. II.A): wave-wide min and sum of the walker's counts
     if (inc) {
-        uint32_t mn = 0xffffffffu, slo = 0, shi = 0;
-        uint64_t sum = 0;
+        // minimum and sum of the counts over the levels that occur (relative to cw
+        // with LDS placement, absolute with HG)
+        uint64_t mn = ~0ull, sum = 0;
         for (int i = lane + kPad; i < WB + kPad; i += 64) {
-            const uint32_t v = lH[i];
-            mn = v < mn ? v : mn;
-            sum += v == 0xffffffffu ? 0u : v;
+            if (HG) {
+                if (!occurs(i)) continue;
+                const uint64_t v = gH[i - kPad];
+                mn = v < mn ? v : mn;
+                sum += v;
+            } else {
+                const uint32_t v = lH[i];
+                if (v == 0xffffffffu) continue;
+                mn = v < mn ? v : mn;
+                sum += v;
+            }
         }
-        slo = (uint32_t)sum;
-        shi = (uint32_t)(sum >> 32);
         for (int off = 32; off > 0; off >>= 1) {
-            const uint32_t m2 = (uint32_t)__shfl_xor((int)mn, off);
-            const uint32_t l2 = (uint32_t)__shfl_xor((int)slo, off);
-            const uint32_t h2 = (uint32_t)__shfl_xor((int)shi, off);
+            const uint64_t m2 = shfl_xor_u64(mn, off), s2 = shfl_xor_u64(sum, off);
             mn = m2 < mn ? m2 : mn;
-            const uint64_t s2 = (((uint64_t)shi << 32) | slo) + (((uint64_t)h2 << 32) | l2);
-            slo = (uint32_t)s2;
-            shi = (uint32_t)(s2 >> 32);
+            sum += s2;
         }
         if (lane == 0) {
-            const uint64_t tot = ((uint64_t)shi << 32) | slo;
             const int64_t n = I.nreach[a];
-            if (walker_flat(I, (uint64_t)mn + cw, tot + (uint64_t)n * cw, n, k)) I.flat[slot] = 1;
+            if (walker_flat(I, mn + cw, sum + (uint64_t)n * cw, n, k)) I.flat[slot] = 1;
         }
     }
 }
@@ -714,12 +765,22 @@ __global__ void __launch_bounds__(512) k_sweep_wave(const Inst* __restrict__ ins
     const Inst& I = insts[tile.inst];
     if (I.ctr->all_done) return;
     const bool wide = I.N > kWaveMapMax;
-    if (I.model == 0) {
-        if (wide) sweep_wave<0, true>(I, tile, smem);
-        else sweep_wave<0, false>(I, tile, smem);
+    if (I.hglobal) {
+        if (I.model == 0) {
+            if (wide) sweep_wave<0, true, true>(I, tile, smem);
+            else sweep_wave<0, false, true>(I, tile, smem);
+        } else {
+            if (wide) sweep_wave<1, true, true>(I, tile, smem);
+            else sweep_wave<1, false, true>(I, tile, smem);
+        }
     } else {
-        if (wide) sweep_wave<1, true>(I, tile, smem);
-        else sweep_wave<1, false>(I, tile, smem);
+        if (I.model == 0) {
+            if (wide) sweep_wave<0, true, false>(I, tile, smem);
+            else sweep_wave<0, false, false>(I, tile, smem);
+        } else {
+            if (wide) sweep_wave<1, true, false>(I, tile, smem);
+            else sweep_wave<1, false, false>(I, tile, smem);
+        }
     }
 }
 
@@ -897,9 +958,10 @@ __global__ void __launch_bounds__(256) k_exchange(const Inst* __restrict__ insts
 }
 
 // ----------------------------------------------------------------- advance
-__global__ void k_advance(const Inst* __restrict__ insts, int n_inst)
+__global__ void k_advance(const Inst* __restrict__ insts, int n_inst, int32_t* __restrict__ queue)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) *queue = 0;                 // the persistent sweep's tile queue
     if (i >= n_inst) return;
     InstCtr* c = insts[i].ctr;
     if (!c->stopped) {

@@ -115,18 +115,29 @@ SMALL = [
 ]
 
 
-def _tune(rw, kind, wpb=0, graph=0, poll=8):
-    return rw.make_tune(kind, wpb, graph, poll)
+def _tune(rw, kind, wpb=0, graph=0, poll=8, placement="auto"):
+    persistent = 0
+    if kind == "wave-device":
+        kind, placement = "wave", "device"
+    if kind == "lane-persist":
+        kind, persistent = "lane", 1
+    return rw.make_tune(kind, wpb, graph, poll, table_placement=placement, persistent=persistent)
 
 
-@pytest.mark.parametrize("kind", ["lane", "wave"])
+@pytest.mark.parametrize("kind", ["lane", "lane-persist", "wave", "wave-device"])
 @pytest.mark.parametrize("kw", SMALL, ids=lambda kw: f"{kw['model']}-L{kw['L']}-h{kw['n_windows']}-m{kw['m']}"
                                                    f"{'-' + kw['flat_rule'] if 'flat_rule' in kw else ''}"
                                                    f"{'-windows' if 'windows' in kw else ''}")
 def test_lockstep_small(rw, kw, kind):
+    """Lane sweep (one block per tile, or a persistent grid over a tile queue), wave
+    sweep with the counts in LDS, and wave sweep with the counts read from device
+    memory: each bit-identical to the oracle."""
     steps = 40 if kw["X"] > 1 else 3000
     gpu, _, _ = _lockstep(rw, kw, steps, tune=_tune(rw, kind), every=1 if kw["X"] > 1 else 500)
-    assert gpu.info()["sweep_kind"] == kind          # every lattice here fits either variant
+    info = gpu.info()
+    assert info["sweep_kind"] == kind.split("-")[0]          # every lattice here fits either variant
+    if kind == "wave-device":
+        assert info["table_placement"] == "device"
 
 
 def test_ising_L8_full_run_bitwise(rw):
@@ -262,16 +273,17 @@ def test_batch64_first_interval_autotuned(rw):
 WIDE_BAND = [SMALL[1], SMALL[2], SMALL[3], SMALL[5], SMALL[6], SMALL[10], SMALL[12]]
 
 
-@pytest.mark.parametrize("kind", ["lane", "wave"])
+@pytest.mark.parametrize("kind", ["lane", "wave", "wave-device"])
 @pytest.mark.parametrize("kw", WIDE_BAND, ids=lambda kw: f"{kw['model']}-L{kw['L']}-m{kw['m']}-seed{kw['seed']}")
 def test_lockstep_wide_guard_band(rw, kw, kind):
     """Guard band widened from 2^-40 to 2^-6: hundreds to thousands of decisions per run
     fall inside it and are taken by the double-double slow path (the lane sweep's per-lane branch,
     the wave sweep's in-order re-decision loop, the exchange); every decision is exact,
     so the run must stay bit-identical to the oracle."""
-    tune = rw.make_tune(kind, 0, 0, 8, guard_band_log2=-6)
+    tune = rw.make_tune(kind.split("-")[0], 0, 0, 8, guard_band_log2=-6,
+                        table_placement="device" if kind == "wave-device" else "auto")
     gpu, _, _ = _lockstep(rw, kw, 25, tune=tune, every=5)
-    assert gpu.info()["sweep_kind"] == kind
+    assert gpu.info()["sweep_kind"] == kind.split("-")[0]
     assert gpu.stats()["slow_decisions"] > 500
 
 
@@ -289,7 +301,7 @@ def test_default_guard_band_rarely_used(rw):
     dict(model="potts", q=10, L=32, n_windows=32, m=128, kfinal=10, X=10000, seed=1, flat_rule="visits",
          flat=(0, 1)),
 ], ids=["ising-L64-h16-m64", "potts-q10-L32-h32-m128"])
-@pytest.mark.parametrize("kind", ["auto", "lane"])
+@pytest.mark.parametrize("kind", ["auto", "lane", "wave-device"])
 def test_full_size_merges_to_done(rw, kw, kind):
     """The full-size workloads with Eq. (8) at a = 0: every walker passes at every
     interval, so all windows merge (m = 64 / 128 walkers of 864 / 236 bins) at every
@@ -303,7 +315,7 @@ def test_full_size_merges_to_done(rw, kw, kind):
     dict(model="ising", L=16, n_windows=4, m=64, kfinal=7, X=2000, seed=3),
     dict(model="potts", q=4, L=8, n_windows=3, m=128, kfinal=5, X=1000, seed=5),
 ], ids=["ising-L16-m64", "potts-q4-L8-m128"])
-@pytest.mark.parametrize("kind", ["lane", "wave"])
+@pytest.mark.parametrize("kind", ["lane", "wave", "wave-device"])
 def test_staggered_convergence_with_frozen_windows(rw, kw, kind):
     """m = 64 / 128 walkers per window run to the end under the 80 % rule; windows
     converge hundreds of intervals apart, so converged windows walk frozen and keep
@@ -319,7 +331,7 @@ def test_staggered_convergence_with_frozen_windows(rw, kw, kind):
 
 
 # ----------------------------------------------------------- batch graph replay
-@pytest.mark.parametrize("kind", ["lane", "wave"])
+@pytest.mark.parametrize("kind", ["lane", "lane-persist", "wave", "wave-device"])
 def test_batch_graph_replay_mixed(rw, kind):
     """A mixed batch replays its captured interval graph for 60 intervals, with host
     syncs, state reads and eager oracle work between replays; every replay's result
@@ -365,7 +377,7 @@ def _ckpt_H_offset(rw, g, cfg):
     return 16 + lat + S * 4, (S, WB)
 
 
-@pytest.mark.parametrize("kind", ["lane", "wave"])
+@pytest.mark.parametrize("kind", ["lane", "wave", "wave-device"])
 def test_counts_past_2_32_bitwise(rw, kind):
     """Every walker's counts raised by C = 2^32 + 2^31 + 12345 at every occurring level
     of its window (the oracle's ln g raised by C 2^-k to match), written into a
@@ -406,11 +418,11 @@ def test_counts_past_2_32_bitwise(rw, kind):
 
 def test_count_spread_past_2_32_is_reported(rw):
     """One level of one walker raised by 2^32: the walker's counts now spread over more
-    than the 32-bit range that a sweep keeps per level, and the run stops with
+    than the 32-bit range that a sweep keeps per level in LDS, and the run stops with
     REWL_E_OVERFLOW instead of continuing on wrapped counts."""
     kw = dict(model="ising", L=8, n_windows=2, m=2, k0=10, kfinal=20, X=500, seed=73)
     gc = rw.make_config(**kw)
-    g = rw.Rewl([gc])
+    g = rw.Rewl([gc], tune=_tune(rw, "wave", placement="lds"))
     g.run(2)
     blob = bytearray(rw.rewl_checkpoint(g.h))
     off, shape = _ckpt_H_offset(rw, g, gc)
