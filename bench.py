@@ -52,7 +52,8 @@ LABELS = {
 
 # rocprofv3 summaries holding the HBM byte counters of a workload's sweep kernel
 PROFILES = {"ising64": "k_sweep_wave_ising_L64.txt", "potts32": "k_sweep_wave_potts_q10_L32.txt",
-            "batch64": "k_sweep_k_rng_batch64_lane_lds53.txt"}
+            "batch64": "k_sweep_persist_k_rng_batch64_lane_lds53.txt",
+            "ising128": "k_sweep_wave_device_ising_L128.txt"}
 KERNEL_SOURCES = ("paper_1407_5140_amd/csrc/rewl_kernels.hip", "paper_1407_5140_amd/csrc/rewl_device.hpp")
 
 
@@ -75,6 +76,13 @@ def profiled_traffic(wl: str, kernel: str):
             if kv["source_sha256"] == h.hexdigest()[:16]:
                 return int(kv["read_bytes"]), int(kv["write_bytes"])
     return None
+
+
+def sweep_kernel(info: dict, tune: dict) -> str:
+    """Name of the sweep kernel a handle launches (the one the roofline is taken on)."""
+    if info["sweep_kind"] == "wave":
+        return "k_sweep_wave"
+    return "k_sweep_persist" if tune["persistent"] else "k_sweep"
 
 
 def workload(name: str) -> list:
@@ -278,15 +286,20 @@ def exchange_study(rw, args) -> dict:
             kws.append(dict(base, X=X, seed=100 + sd, exchange=(mode == "exchange")))
             tags.append((mode, X))
     log = lambda m: print(f"[exchange] {m}", file=sys.stderr, flush=True)
-    g, res = Wm.run_to_convergence(kws, args.max_seconds, log=log)
+    g, res = Wm.run_to_convergence(kws, args.max_seconds, tune=rw.make_tune(use_graph=1, poll_every=50),
+                                   log=log)
+    trips = [int(g.stats(i)["round_trips_total"]) for i in range(len(kws))]
     g.close()
     rows = []
     for mode, X in settings:
-        att = [r["intervals"] * X for r, t in zip(res, tags) if t == (mode, X) and r["converged"]]
-        n_conv = sum(1 for r, t in zip(res, tags) if t == (mode, X) and r["converged"])
-        rows.append({"exchange": mode == "exchange", "X": X, "converged": n_conv,
+        sel = [i for i, t in enumerate(tags) if t == (mode, X)]
+        att = [res[i]["intervals"] * X for i in sel if res[i]["converged"]]
+        rows.append({"exchange": mode == "exchange", "X": X, "converged": sum(res[i]["converged"] for i in sel),
                      "attempts_per_walker": att,
-                     "median": float(np.median(att)) if att else None})
+                     "min_k_unconverged": [res[i]["min_k"] for i in sel if not res[i]["converged"]],
+                     "attempts_unconverged": [res[i]["intervals"] * X for i in sel if not res[i]["converged"]],
+                     "round_trips": [trips[i] for i in sel],
+                     "median": float(np.median(att)) if len(att) == len(sel) else None})
     ref = next(r for r in rows if not r["exchange"])["median"]
     for r in rows:
         r["speedup_vs_no_exchange"] = (ref / r["median"]) if (ref and r["median"]) else None
@@ -666,6 +679,7 @@ def main(argv=None):
                     help="only copy a device buffer of this size and exit (a kernel of known "
                          "traffic for scaling the HBM byte counters)")
     ap.add_argument("--wpb", type=int, default=0, help="walkers per block (0 = library choice)")
+    ap.add_argument("--persistent", action="store_true", help="lane sweep: persistent grid over a tile queue")
     ap.add_argument("--placement", default="auto", choices=["auto", "lds", "device"],
                     help="wave sweep: where the walkers' counts live while it runs")
     ap.add_argument("--lds-kb", type=int, default=0,
@@ -804,7 +818,8 @@ def main(argv=None):
     # intervals); the kernel times come from a second pass of the same length with
     # per-launch events, which synchronises the host once per interval
     tune = rw.make_tune(args.sweep, args.wpb, 1, 1 << 20, lds_target_kb=args.lds_kb,
-                        autotune=1 if args.autotune else 0, table_placement=args.placement)
+                        autotune=1 if args.autotune else 0, table_placement=args.placement,
+                        persistent=1 if args.persistent else 0)
     g = rw.Rewl(cfgs, tune=tune)
     t_create = time.perf_counter() - t_create
     info = g.info()
@@ -828,7 +843,7 @@ def main(argv=None):
     sweep_ms = (st1["sweep_ms"] - st0["sweep_ms"]) / args.steps
     interval_ms = (st1["interval_ms"] - st0["interval_ms"]) / args.steps
     ops = sum(OPS_PER_ATTEMPT[kw["model"]] * kw["n_windows"] * kw["m"] * kw["X"] for kw in kws)
-    kernel = "k_sweep_wave" if info["sweep_kind"] == "wave" else "k_sweep"
+    kernel = sweep_kernel(info, g.tune())
     traffic = profiled_traffic(args.workload, kernel)
     achieved = ops / (sweep_ms * 1e-3)
     print(f"[bench] {args.steps} intervals in {dt:.3f} s: {value:.4g} attempts/s; sweep "
@@ -892,6 +907,8 @@ def batch_line(rw, steps: int = 10, warmup: int = 2) -> dict:
     interval_ms = (st1["interval_ms"] - st0["interval_ms"]) / steps
     info, tune = g.info(), g.tune()
     g.close()
+    kernel = sweep_kernel(info, tune)
+    traffic = profiled_traffic("batch64", kernel)
     print(f"[bench] batch64: {att / dt:.4g} attempts/s, sweep {sweep_ms:.3f} ms/launch, interval "
           f"{interval_ms:.3f} ms, tune {tune}, create+autotune {t_create:.2f} s", file=sys.stderr, flush=True)
     return {"workload": LABELS["batch64"], "attempts_per_s": att / dt, "ms_per_step": dt * 1e3 / steps,
@@ -900,7 +917,9 @@ def batch_line(rw, steps: int = 10, warmup: int = 2) -> dict:
             "roofline": {"bound": "alu", "achieved": ops / steps / (sweep_ms * 1e-3) / 1e12,
                          "peak": PEAK_LANE_OPS / 1e12, "unit": "Tops/s",
                          "frac": ops / steps / (sweep_ms * 1e-3) / PEAK_LANE_OPS,
-                         "kernel": "k_sweep" if info["sweep_kind"] == "lane" else "k_sweep_wave"}}
+                         "traffic": None if traffic is None else sum(traffic),
+                         "traffic_read_write": traffic, "kernel": kernel,
+                         "persistent": bool(tune["persistent"])}}
 
 
 def ising8_converge(rw, seeds=(1, 2, 3)) -> dict:

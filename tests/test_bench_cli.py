@@ -23,10 +23,15 @@ def test_profiled_traffic_requires_matching_sources(monkeypatch):
     # counts) or it does not (None); a wrong kernel name never matches
     assert got is None or (len(got) == 2 and all(v > 0 for v in got))
     assert bench.profiled_traffic("ising64", "no_such_kernel") is None
-    for k in ("k_sweep", "k_rng"):
+    for k in ("k_sweep_persist", "k_rng"):
         got = bench.profiled_traffic("batch64", k)
         assert got is None or (len(got) == 2 and all(v > 0 for v in got))
     assert bench.profiled_traffic("potts100", "k_sweep_wave") is None     # no summary committed
+    # the persistent and the plain lane sweep are different kernels
+    info = {"sweep_kind": "lane"}
+    assert bench.sweep_kernel(info, {"persistent": 1}) == "k_sweep_persist"
+    assert bench.sweep_kernel(info, {"persistent": 0}) == "k_sweep"
+    assert bench.sweep_kernel({"sweep_kind": "wave"}, {"persistent": 1}) == "k_sweep_wave"
 
 
 def test_ground_tilted_windows_are_a_valid_layout():
