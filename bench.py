@@ -580,6 +580,76 @@ def headline_study(rw, args) -> dict:
     return out
 
 
+def target_study(rw, args) -> dict:
+    """Warm start against plain REWL on a large target at equal GPU time.
+
+    The network is trained on REWL's own results (ln f -> 2^-16) for every type of
+    the 64-instance batch with L <= 48, produced in this run.  The target then runs
+    once plain (ln f from 1) and once per warm k0 (the network's table, ln f from
+    2^-k0), all as instances of one handle, so that every sweep launch covers all of
+    them and they share one clock.  Reported: per-window k of every instance at
+    regular times, and the first time each instance had every window at k >= K."""
+    from paper_1407_5140_amd import warm as Wm
+    log = lambda m: print(f"[target] {m}", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    kws = Wm.training_workload(Wm.TRAIN_TYPES, m=32, kfinal=16)
+    g, res = Wm.run_to_convergence(kws, args.max_seconds, log=log)
+    okr = [r["converged"] for r in res]
+    x, t = Wm.training_rows(g, kws, okr)
+    g.close()
+    t_data = time.perf_counter() - t0
+    net, info = Wm.train(x, t, steps=args.mlp_steps, batch=4096, lr=1e-3)
+    log(f"training: {sum(okr)}/{len(kws)} instances, {len(t)} rows, {t_data:.1f} s; network {info}")
+    target = dict(workload(args.ts_target)[0], seed=args.ts_seed)
+    if args.windows == "tilted":
+        target["windows"] = tilted_windows(rw, target)
+    tab = Wm.warm_table(net, target)
+    net.close()
+    k0s = [0] + [Wm.suggest_k0(info["rms"], target["L"] ** 2) if int(v) < 0 else int(v)
+                 for v in args.ts_k0.split(",")]
+    cfgs = [rw.make_config(**dict(target, k0=k0)) for k0 in k0s]
+    gg = rw.Rewl(cfgs, tune=rw.make_tune(autotune=1, use_graph=1, poll_every=1 << 20))
+    for i, k0 in enumerate(k0s):
+        if k0 > 0:
+            gg.set_initial_lng(tab, i)
+    log(f"{args.ts_target}: instances with k0 {k0s}, tune {gg.tune()}, info {gg.info()}")
+    h = target["n_windows"]
+    reached = [dict() for _ in k0s]          # K -> (seconds, intervals) of the first all-windows >= K
+    samples, last = [], -1e9
+    ts = time.perf_counter()
+    while True:
+        all_done = gg.run(200)
+        now = time.perf_counter() - ts
+        sts = [gg.stats(i) for i in range(len(k0s))]
+        for i, st in enumerate(sts):
+            for K in range(0, min(st["k"]) + 1):
+                reached[i].setdefault(K, (now, st["intervals"]))
+        if now - last >= args.ts_sample or all_done or now > args.ts_seconds:
+            samples.append({"seconds": now, "intervals": sts[0]["intervals"],
+                            "k": [[int(v) for v in st["k"]] for st in sts],
+                            "round_trips": [int(st["round_trips_total"]) for st in sts]})
+            log(f"{now:.0f} s, {sts[0]['intervals']} intervals: min k {[min(st['k']) for st in sts]}, "
+                f"mean k {[round(float(np.mean(st['k'])), 2) for st in sts]}, windows done "
+                f"{[int(st['windows_done']) for st in sts]}/{h}")
+            last = now
+        if all_done or now > args.ts_seconds:
+            break
+    gg.close()
+    names = ["plain"] + [f"warm k0={k0}" for k0 in k0s[1:]]
+    levels = sorted(set().union(*[r.keys() for r in reached]))
+    first = {str(K): [reached[i].get(K, (None, None))[0] for i in range(len(k0s))] for K in levels}
+    # plain's time to reach K on every window over each warm instance's
+    ratio = {names[i]: {K: v[0] / v[i] for K, v in first.items() if v[0] is not None and v[i]}
+             for i in range(1, len(k0s))}
+    return {"mode": "warm start vs plain at equal GPU time, one handle",
+            "workload": f"{LABELS.get(args.ts_target, args.ts_target)}; windows {args.windows}; "
+                        f"ln f 1 (plain) or 2^-k0 (warm) -> 2^-{target['kfinal']}; seed {args.ts_seed}",
+            "instances": names, "k0": k0s, "seconds_limit": args.ts_seconds,
+            "train": {"types": Wm.TRAIN_TYPES, "converged": int(sum(okr)), "rows": int(len(t)),
+                      "seconds": t_data}, "network": info,
+            "first_all_windows_at_k": first, "plain_over_warm_at_k": ratio, "samples": samples}
+
+
 def accuracy_study(rw, args) -> dict:
     """Where the DOS error of Ising runs comes from (Sec. II.B joins against the pieces
     themselves), judged against the exact DOS.  n seeds of one workload run in one
@@ -680,6 +750,8 @@ def main(argv=None):
                          "traffic for scaling the HBM byte counters)")
     ap.add_argument("--wpb", type=int, default=0, help="walkers per block (0 = library choice)")
     ap.add_argument("--persistent", action="store_true", help="lane sweep: persistent grid over a tile queue")
+    ap.add_argument("--map-log2", type=int, default=0,
+                    help="wave sweep: at most 2^v site-map entries per walker (6..12; 0 = library's choice)")
     ap.add_argument("--placement", default="auto", choices=["auto", "lds", "device"],
                     help="wave sweep: where the walkers' counts live while it runs")
     ap.add_argument("--lds-kb", type=int, default=0,
@@ -716,6 +788,13 @@ def main(argv=None):
     ap.add_argument("--hl-kfinal", type=int, default=27)
     ap.add_argument("--hl-seeds", type=int, default=8)
     ap.add_argument("--hl-flat", default="19,20")
+    ap.add_argument("--target-study", action="store_true",
+                    help="warm start against plain on a large target at equal GPU time")
+    ap.add_argument("--ts-target", default="potts64")
+    ap.add_argument("--ts-k0", default="-1,10", help="warm k0 values (-1: from the network's error)")
+    ap.add_argument("--ts-seconds", type=float, default=900.0)
+    ap.add_argument("--ts-sample", type=float, default=30.0)
+    ap.add_argument("--ts-seed", type=int, default=1)
     ap.add_argument("--accuracy-study", action="store_true",
                     help="split the DOS error of Ising runs into piece shape and join parts (exact DOS)")
     ap.add_argument("--acc-L", type=int, default=32)
@@ -782,6 +861,9 @@ def main(argv=None):
     if args.ensemble_study:
         print(json.dumps(ensemble_study(rw, args)), flush=True)
         return 0
+    if args.target_study:
+        print(json.dumps(target_study(rw, args)), flush=True)
+        return 0
     if args.accuracy_study:
         print(json.dumps(accuracy_study(rw, args)), flush=True)
         return 0
@@ -819,11 +901,12 @@ def main(argv=None):
     # per-launch events, which synchronises the host once per interval
     tune = rw.make_tune(args.sweep, args.wpb, 1, 1 << 20, lds_target_kb=args.lds_kb,
                         autotune=1 if args.autotune else 0, table_placement=args.placement,
-                        persistent=1 if args.persistent else 0)
+                        persistent=1 if args.persistent else 0, map_log2=args.map_log2)
     g = rw.Rewl(cfgs, tune=tune)
     t_create = time.perf_counter() - t_create
     info = g.info()
-    print(f"[bench] {label}: {S} walkers, {info['sweep_kind']} sweep ({info['table_placement']} counts), "
+    print(f"[bench] {label}: {S} walkers, {info['sweep_kind']} sweep ({info['table_placement']} counts, "
+          f"{info['map_entries']} map entries), "
           f"walkers/block {info['walkers_per_block']}, "
           f"LDS {info['lds_bytes']} B, tune {g.tune()}, create {t_create:.2f} s", file=sys.stderr, flush=True)
 
@@ -865,7 +948,7 @@ def main(argv=None):
         "data": "synthetic",
         "config": {"workload": label, "walkers": S, "attempts_per_step": att_step, "graph": True,
                    "sweep": info["sweep_kind"], "walkers_per_block": info["walkers_per_block"],
-                   "table_placement": info["table_placement"]},
+                   "table_placement": info["table_placement"], "map_entries": info["map_entries"]},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
                      "unit": "Tops/s", "frac": achieved / PEAK_LANE_OPS,
                      "traffic": None if traffic is None else sum(traffic),

@@ -97,8 +97,10 @@ enum { REWL_SWEEP_AUTO = 0, REWL_SWEEP_LANE = 1, REWL_SWEEP_WAVE = 2 };
  * memory, read when the walker's 64-bin register window of ln g is loaded and
  * written when it moves (a few times per thousand attempts), so LDS holds only the
  * window's base table, the site maps and the lattices, and more walkers fit a
- * block on large lattices.  AUTO: DEVICE where it fits more walkers per block,
- * else LDS.  Both give bit-identical results; the LANE sweep always uses LDS.    */
+ * block on large lattices.  AUTO: chosen with the site-map size (rewl_tune
+ * map_log2) and the walkers per block so that as many of the instance's walkers
+ * as possible are resident on the GPU at once; on a tie the larger site map, then
+ * LDS.  Both give bit-identical results; the LANE sweep always uses LDS.         */
 enum { REWL_TABLE_AUTO = 0, REWL_TABLE_LDS = 1, REWL_TABLE_DEVICE = 2 };
 
 /* Optional tuning of a batch (NULL = library choice). */
@@ -124,6 +126,17 @@ typedef struct {
                                    holds at once, each taking tiles (longest first) from
                                    a device-side queue until none is left; 0 = one
                                    block per tile, handed out by the hardware          */
+    int32_t map_log2;           /* WAVE sweep: at most 2^map_log2 site-map entries per
+                                   walker (6..12); 0 = auto.  The map marks which
+                                   attempts of a 64-attempt chunk lie in one another's
+                                   neighbourhoods; a lattice with more sites than
+                                   entries shares an entry between the sites equal
+                                   modulo the entry count, which only marks extra
+                                   attempts for re-evaluation (results stay
+                                   bit-identical) but frees LDS for more resident
+                                   walkers.  Auto takes the largest map among 2^12 ..
+                                   2^9 entries that keeps the most walkers resident,
+                                   with the placement above.                            */
 } rewl_tune;
 
 typedef struct rewl_handle rewl_handle;
@@ -297,10 +310,12 @@ const char* rewl_last_error(void);
 rewl_status rewl_get_tune(rewl_handle* h, rewl_tune* out);
 
 /* Number of instances, and for one instance the sweep variant chosen
- * (REWL_SWEEP_LANE / _WAVE), walkers per block, LDS bytes per block and the
- * count table's placement (REWL_TABLE_LDS / _DEVICE).  Any pointer may be NULL. */
+ * (REWL_SWEEP_LANE / _WAVE), walkers per block, LDS bytes per block, the count
+ * table's placement (REWL_TABLE_LDS / _DEVICE) and the WAVE sweep's site-map
+ * entries per walker (0 for LANE).  Any pointer may be NULL.                     */
 rewl_status rewl_info(rewl_handle* h, int32_t instance, int32_t* n_instances, int32_t* sweep_kind,
-                      int32_t* walkers_per_block, size_t* lds_bytes, int32_t* table_placement);
+                      int32_t* walkers_per_block, size_t* lds_bytes, int32_t* table_placement,
+                      int32_t* map_entries);
 
 /* Diagnostics (run on the device, used by the tests):
  * the full acceptance predicate u53 < 2^53 exp(delta) for n pairs: out[i] =

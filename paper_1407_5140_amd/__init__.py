@@ -53,21 +53,24 @@ class rewl_tune(ctypes.Structure):
                 ("poll_every", ctypes.c_int32), ("sweep_kind", ctypes.c_int32),
                 ("lds_target_kb", ctypes.c_int32), ("autotune", ctypes.c_int32),
                 ("guard_band_log2", ctypes.c_int32), ("table_placement", ctypes.c_int32),
-                ("persistent", ctypes.c_int32)]
+                ("persistent", ctypes.c_int32), ("map_log2", ctypes.c_int32)]
 
 
 PLACEMENTS = {"auto": 0, "lds": 1, "device": 2}
 
 
 def make_tune(kind="auto", walkers_per_block=0, use_graph=0, poll_every=8, lds_target_kb=0,
-              autotune=0, guard_band_log2=0, table_placement="auto", persistent=0) -> rewl_tune:
+              autotune=0, guard_band_log2=0, table_placement="auto", persistent=0,
+              map_log2=0) -> rewl_tune:
     """guard_band_log2: 0 keeps the library's 2^-40 guard band of the fast acceptance
     test; -40..-2 widen it (identical results, more exact slow-path decisions).
     table_placement: where the wave sweep keeps the counts ("lds", "device", "auto");
-    persistent: 1 runs the lane sweep as a persistent grid over a tile queue."""
+    persistent: 1 runs the lane sweep as a persistent grid over a tile queue;
+    map_log2: the wave sweep's site map holds at most 2^map_log2 entries per walker
+    (6..12; 0 = the library's choice)."""
     return rewl_tune(walkers_per_block, use_graph, poll_every,
                      {"auto": 0, "lane": 1, "wave": 2}[kind], lds_target_kb, autotune, guard_band_log2,
-                     PLACEMENTS[table_placement], persistent)
+                     PLACEMENTS[table_placement], persistent, map_log2)
 
 
 class rewl_stats(ctypes.Structure):
@@ -102,7 +105,7 @@ _sigs = {
     "rewl_checkpoint": ([_vp, _vp, _P(ctypes.c_size_t)], ctypes.c_int),
     "rewl_restore": ([_vp, _vp, ctypes.c_size_t], ctypes.c_int),
     "rewl_destroy": ([_vp], None),
-    "rewl_info": ([_vp, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
+    "rewl_info": ([_vp, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
     "rewl_get_tune": ([_vp, _P(rewl_tune)], ctypes.c_int),
     "rewl_probe_accept": ([_vp, _vp, ctypes.c_int32, _vp], ctypes.c_int),
     "rewl_probe_philox": ([_vp, ctypes.c_int32, _vp], ctypes.c_int),
@@ -331,12 +334,13 @@ def rewl_destroy(h) -> None:
 
 
 def rewl_info(h, instance: int = 0) -> dict:
-    n, kind, w, lds, pl = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_size_t(), ctypes.c_int32()
+    n, kind, w, lds = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_size_t()
+    pl, mp = ctypes.c_int32(), ctypes.c_int32()
     _check(_lib.rewl_info(h, instance, ctypes.byref(n), ctypes.byref(kind), ctypes.byref(w),
-                          ctypes.byref(lds), ctypes.byref(pl)), "rewl_info")
+                          ctypes.byref(lds), ctypes.byref(pl), ctypes.byref(mp)), "rewl_info")
     return dict(n_instances=n.value, sweep_kind={1: "lane", 2: "wave"}[kind.value],
                 walkers_per_block=w.value, lds_bytes=lds.value,
-                table_placement={1: "lds", 2: "device"}[pl.value])
+                table_placement={1: "lds", 2: "device"}[pl.value], map_entries=mp.value)
 
 
 def rewl_get_tune(h) -> dict:

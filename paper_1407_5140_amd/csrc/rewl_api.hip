@@ -138,7 +138,7 @@ rewl_status validate(const rewl_config& c)
 
 struct HostInst {
     rewl_config cfg;
-    int N, W, h, m, S, WB, log2m, wpr, wpb, kind, placement;
+    int N, W, h, m, S, WB, log2m, wpr, wpb, kind, placement, mapn;
     size_t lds;
     std::vector<int32_t> lo, hi, nreach;
     std::vector<uint8_t> mask;
@@ -456,9 +456,16 @@ static rewl_status create_impl(const rewl_config* cfgs, int32_t n, void* hip_str
     }
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
-    int lds_limit = 0;
+    int lds_limit = 0, n_cu = 0;
     HIP_TRY(hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    HIP_TRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
     if (lds_limit <= 0) lds_limit = 65536;
+    if (n_cu <= 0) n_cu = 1;
+    // waves of the wave sweep a CU holds at once as far as registers allow
+    // (one-wave blocks without LDS)
+    int wave_cap = 0;
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&wave_cap, (const void*)k_sweep_wave, 64, 0));
+    if (wave_cap <= 0) wave_cap = 1;
 
     if (tune && tune->guard_band_log2 != 0 && (tune->guard_band_log2 < -40 || tune->guard_band_log2 > -2))
         return fail(REWL_E_INVALID, "guard_band_log2 must be 0 (2^-40) or in [-40, -2]");
@@ -466,6 +473,8 @@ static rewl_status create_impl(const rewl_config* cfgs, int32_t n, void* hip_str
         return fail(REWL_E_INVALID, "table_placement must be REWL_TABLE_AUTO, _LDS or _DEVICE");
     if (tune && tune->persistent != 0 && tune->persistent != 1)
         return fail(REWL_E_INVALID, "persistent must be 0 or 1");
+    if (tune && tune->map_log2 != 0 && (tune->map_log2 < 6 || tune->map_log2 > 12))
+        return fail(REWL_E_INVALID, "map_log2 must be 0 (auto) or in [6, 12]");
     rewl_handle* H = new rewl_handle();
     H->device = dev;
     if (tune) H->tune = *tune;
@@ -517,7 +526,8 @@ static rewl_status create_impl(const rewl_config* cfgs, int32_t n, void* hip_str
         // 3.50 ms per 10^4 attempts); with tens of thousands of walkers the lane
         // variant's width wins (the 64-instance batch).
         // any lattice, as long as one walker's wave tables fit (the site map is bounded)
-        const bool wave_ok = wave_lds_bytes(c.model, c.L, hi.WB, 1, true) <= (size_t)lds_limit;
+        const bool wave_ok =
+            wave_lds_bytes(c.model, c.L, hi.WB, 1, true, wave_map_entries(hi.N, 9)) <= (size_t)lds_limit;
         int64_t total_walkers = 0;
         for (int u = 0; u < n; ++u) total_walkers += (int64_t)cfgs[u].n_windows * cfgs[u].walkers_per_window;
         hi.kind = REWL_SWEEP_LANE;
@@ -539,23 +549,45 @@ static rewl_status create_impl(const rewl_config* cfgs, int32_t n, void* hip_str
             int want = H->tune.walkers_per_block > 0 ? H->tune.walkers_per_block : 4;
             int G0 = 1;
             while (G0 * 2 <= std::min(want, std::min(8, hi.m))) G0 *= 2;
-            // walkers per block that fit with the counts in LDS and in device memory
-            auto fit = [&](bool hg) {
-                int G = G0;
-                while (G > 1 && wave_lds_bytes(c.model, c.L, hi.WB, G, hg) > (size_t)lds_limit) G /= 2;
-                return wave_lds_bytes(c.model, c.L, hi.WB, G, hg) <= (size_t)lds_limit ? G : 0;
-            };
-            const int g_lds = fit(false), g_glob = fit(true);
-            bool hg;
-            if (H->tune.table_placement == REWL_TABLE_LDS && g_lds > 0) hg = false;
-            else if (H->tune.table_placement == REWL_TABLE_DEVICE) hg = true;
-            else hg = g_glob > g_lds;          // auto: device memory only where it fits more walkers
-            const int G = hg ? g_glob : g_lds;
-            hi.placement = hg ? REWL_TABLE_DEVICE : REWL_TABLE_LDS;
-            hi.wpb = G;
-            hi.lds = wave_lds_bytes(c.model, c.L, hi.WB, G, hg);
+            // Walkers per block, count placement and site-map size: the choice that
+            // keeps the most of this instance's walkers resident at once (fewest
+            // rounds of blocks over the GPU's CUs), then the largest map (fewest
+            // shared entries), then the counts in LDS.
+            struct Choice { int G, mapn; bool hg; size_t lds; int64_t rounds; };
+            Choice best{0, 0, false, 0, INT64_MAX};
+            std::vector<bool> places;
+            if (H->tune.table_placement != REWL_TABLE_DEVICE) places.push_back(false);
+            if (H->tune.table_placement != REWL_TABLE_LDS) places.push_back(true);
+            std::vector<int> maps;
+            if (H->tune.map_log2 > 0) maps.push_back(wave_map_entries(hi.N, H->tune.map_log2));
+            else
+                for (int lg = 12; lg >= 9; --lg) {
+                    const int mn = wave_map_entries(hi.N, lg);
+                    if (maps.empty() || mn < maps.back()) maps.push_back(mn);
+                }
+            for (int mapn : maps)
+                for (bool hg : places) {
+                    int G = G0;
+                    while (G > 1 && wave_lds_bytes(c.model, c.L, hi.WB, G, hg, mapn) > (size_t)lds_limit) G /= 2;
+                    const size_t lds = wave_lds_bytes(c.model, c.L, hi.WB, G, hg, mapn);
+                    if (lds > (size_t)lds_limit) continue;
+                    const int64_t per_cu = std::min<int64_t>((int64_t)lds_limit / (int64_t)lds, wave_cap / G);
+                    const int64_t resident = std::max<int64_t>(1, per_cu * G * n_cu);
+                    const int64_t rounds = (hi.S + resident - 1) / resident;
+                    // candidates come largest map first, LDS before device memory
+                    if (rounds < best.rounds) best = Choice{G, mapn, hg, lds, rounds};
+                }
+            if (best.G == 0) {
+                // one walker's tables exceed the LDS: reported below
+                best = Choice{1, wave_map_entries(hi.N, 0), true, wave_lds_bytes(c.model, c.L, hi.WB, 1, true,
+                                                                                  wave_map_entries(hi.N, 0)), 0};
+            }
+            hi.placement = best.hg ? REWL_TABLE_DEVICE : REWL_TABLE_LDS;
+            hi.wpb = best.G;
+            hi.mapn = best.mapn;
+            hi.lds = best.lds;
             H->max_lds_wave = std::max(H->max_lds_wave, hi.lds);
-            H->wave_threads = std::max(H->wave_threads, 64 * G);
+            H->wave_threads = std::max(H->wave_threads, 64 * best.G);
         }
         if (hi.lds > (size_t)lds_limit)
             return bail(fail(REWL_E_INVALID, "instance " + std::to_string(i) + ": one walker's tables exceed LDS"));
@@ -568,6 +600,7 @@ static rewl_status create_impl(const rewl_config* cfgs, int32_t n, void* hip_str
         d.X = c.exchange_interval; d.k0 = (uint32_t)c.seed; d.k1 = (uint32_t)(c.seed >> 32);
         d.band = band;
         d.hglobal = hi.placement == REWL_TABLE_DEVICE ? 1 : 0;
+        d.mapn = hi.kind == REWL_SWEEP_WAVE ? hi.mapn : 0;
         d.XP = (c.exchange_interval + 31) / 32 * 32;   // two draw chunks of 16
         if ((uint64_t)d.XP * hi.S >= (uint64_t(1) << 32))
             return bail(fail(REWL_E_INVALID, "instance " + std::to_string(i) + ": walkers x interval exceeds 2^32 draws"));
@@ -693,12 +726,11 @@ static rewl_status create_impl(const rewl_config* cfgs, int32_t n, void* hip_str
         return bail(fail(REWL_E_DEVICE, "cannot raise the dynamic LDS limit"));
 
     if (H->ntiles > 0) {
-        int per_cu = 0, n_cu = 0;
+        int per_cu = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_sweep_persist, 64,
-                                                         std::max<size_t>(H->max_lds, 1)) != hipSuccess ||
-            hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+                                                         std::max<size_t>(H->max_lds, 1)) != hipSuccess)
             return bail(fail(REWL_E_DEVICE, "occupancy query failed"));
-        H->persist_grid = std::max(1, std::min(H->ntiles, std::max(per_cu, 1) * std::max(n_cu, 1)));
+        H->persist_grid = std::max(1, std::min(H->ntiles, std::max(per_cu, 1) * n_cu));
     }
     hipLaunchKernelGGL(k_init, dim3((H->slot_threads + 127) / 128), dim3(128), 0, st, H->d_insts,
                        H->d_slot_start, n);
@@ -728,18 +760,25 @@ static rewl_status autotune(const rewl_config* cfgs, int32_t n, void* hip_stream
             t.autotune = 0;
             cand.push_back(t);
         }
+    // wave variant: the library's own choice of walkers per block, placement and
+    // site map (largest map that keeps the most walkers resident), the same with
+    // the full map, and fixed walkers per block and placements
+    struct WaveCand { int g, pl, map_log2; };
+    const WaveCand wave_cands[] = {{0, REWL_TABLE_AUTO, 0}, {0, REWL_TABLE_AUTO, 12},
+                                   {1, REWL_TABLE_LDS, 12},  {1, REWL_TABLE_DEVICE, 12},
+                                   {4, REWL_TABLE_LDS, 12},  {4, REWL_TABLE_DEVICE, 12}};
     if (all_wave)
-        for (int g : {1, 4})
-            for (int pl : {REWL_TABLE_LDS, REWL_TABLE_DEVICE}) {
-                rewl_tune t = base;
-                t.sweep_kind = REWL_SWEEP_WAVE;
-                t.walkers_per_block = g;
-                t.lds_target_kb = 0;
-                t.persistent = 0;
-                t.table_placement = pl;
-                t.autotune = 0;
-                cand.push_back(t);
-            }
+        for (const WaveCand& w : wave_cands) {
+            rewl_tune t = base;
+            t.sweep_kind = REWL_SWEEP_WAVE;
+            t.walkers_per_block = w.g;
+            t.lds_target_kb = 0;
+            t.persistent = 0;
+            t.table_placement = w.pl;
+            t.map_log2 = w.map_log2;
+            t.autotune = 0;
+            cand.push_back(t);
+        }
     double best_ms = 1e300;
     *best = cand[0];
     for (const rewl_tune& t : cand) {
@@ -845,7 +884,7 @@ rewl_status rewl_set_timing(rewl_handle* H, int32_t on)
 }
 
 rewl_status rewl_info(rewl_handle* H, int32_t i, int32_t* n_instances, int32_t* kind, int32_t* wpb,
-                      size_t* lds, int32_t* placement)
+                      size_t* lds, int32_t* placement, int32_t* map_entries)
 {
     rewl_status s = check_inst(H, i);
     if (s != REWL_OK) return s;
@@ -854,6 +893,7 @@ rewl_status rewl_info(rewl_handle* H, int32_t i, int32_t* n_instances, int32_t* 
     if (wpb) *wpb = H->inst[i].wpb;
     if (lds) *lds = H->inst[i].lds;
     if (placement) *placement = H->inst[i].placement;
+    if (map_entries) *map_entries = H->inst[i].kind == REWL_SWEEP_WAVE ? H->inst[i].mapn : 0;
     return REWL_OK;
 }
 

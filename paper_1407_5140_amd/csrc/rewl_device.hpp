@@ -208,7 +208,7 @@ struct Inst {
     int32_t* rt_count;  // [S] per replica: completed round trips 0 -> h-1 -> 0
     double band;        // guard band of the fast acceptance test
     int32_t hglobal;    // wave sweep: counts read from device memory, not an LDS copy
-    int32_t pad_;
+    int32_t mapn;       // wave sweep: site-map entries per walker (N, or a power of two below N)
     InstCtr* ctr;
 };
 

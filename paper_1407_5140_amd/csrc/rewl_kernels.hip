@@ -392,23 +392,27 @@ __global__ void __launch_bounds__(64) k_sweep_persist(const Inst* __restrict__ i
 // One wave per walker, for workloads with few walkers: the walker's Markov
 // chain runs on wave-uniform (scalar) values, and the 64 lanes draw the Philox
 // numbers of the next 64 attempts in parallel (no draw buffer).
-//   Ising (L <= 64): lane y holds lattice row y; rows are read with v_readlane.
-//   Potts: the walker's lattice is one byte per site in LDS (uniform addresses).
-// LDS: base [nbins] shared by the block's walkers (all of one window), then per
-// wave its counts H [nbins], then (Potts) per wave its lattice [N].
-// LDS of the wave variant: the window's base table (shared), then per wave its
-// histogram, its site map and its lattice (Potts bytes, Ising 64-bit words, wpr
-// per row).  The site map has one 64-bit attempt mask per entry, min(N, 4096)
-// entries; larger lattices share entries between sites (site mod 4096), which
-// only adds attempts to the out-of-date sets, never removes one.
+// LDS: the window's base table (shared by the block's walkers, all of one
+// window), then per wave its counts (LDS placement only), then per wave its site
+// map, then per wave its lattice (Potts one byte per site, Ising wpr 64-bit words
+// per row).  The site map holds one 64-bit attempt mask per entry: one entry per
+// site, or M = 2^j < N entries shared by the sites equal modulo M, which only
+// adds attempts to the out-of-date sets, never removes one (so a smaller map
+// trades extra re-evaluations for LDS).
 constexpr int kWaveMapMax = 4096;
-__host__ __device__ inline int wave_map_entries(int N) { return N < kWaveMapMax ? N : kWaveMapMax; }
-__host__ __device__ inline size_t wave_lds_bytes(int model, int L, int WB, int G, bool hglobal = false)
+// site-map entries per walker for a lattice of N sites and a cap of 2^map_log2
+// entries (0: 2^12)
+__host__ __device__ inline int wave_map_entries(int N, int map_log2 = 0)
+{
+    const int cap = 1 << (map_log2 > 0 ? map_log2 : 12);
+    return N <= cap ? N : cap;
+}
+__host__ __device__ inline size_t wave_lds_bytes(int model, int L, int WB, int G, bool hglobal, int mapn)
 {
     const size_t nb = (size_t)WB + 2 * kPad, N = (size_t)L * L;
     size_t s = nb * 8 + (hglobal ? 0 : (size_t)G * nb * 4);
     s = (s + 7) & ~size_t(7);
-    s += (size_t)G * wave_map_entries((int)N) * 8;
+    s += (size_t)G * mapn * 8;
     s += model == 1 ? (size_t)G * N : (size_t)G * L * ((L + 63) / 64) * 8;
     return s;
 }
@@ -456,8 +460,8 @@ __device__ __forceinline__ int ising_d_words(const uint64_t* rows, int wpr, int 
 //   those attempts were rejected or were accepted with d = 0 (a move within the
 //   bin, always accepted).  The run ends at the first accepted move with d != 0,
 //   or before the first attempt that a flip of the run made out of date.
-// WIDE: N > 4096 (site map entries shared mod 4096; Ising rows of several
-// words).  The narrow form keeps the one-word rows and the direct map.
+// WIDE: Ising rows of several 64-bit words (L > 64); the narrow form keeps one
+// word per row.
 // HG: the walker's counts stay in device memory (the 64-bit H array) instead of
 // an LDS copy: they are touched only when the register window is loaded or
 // stored and by the flatness test, so LDS then holds only the window's base table,
@@ -482,14 +486,15 @@ __device__ void sweep_wave(const Inst& I, const Tile& tile, char* smem)
     const int r = tile.r0 + wave, slot = a * I.m + r;
     uint32_t* lH = (uint32_t*)(lbase + nbins) + (size_t)wave * nbins;           // LDS placement only
     uint64_t* gH = I.H + (size_t)slot * WB;                                      // the walker's counts
-    const int M = WIDE ? kWaveMapMax : N;
+    const int M = I.mapn;                                     // site-map entries
+    // site -> map entry: the site itself when every site has one, else site mod M
+    const uint32_t mmask = M >= N ? 0xffffffffu : (uint32_t)(M - 1);
     const int wpr = WIDE ? I.wpr : 1;                         // Ising words per row
     const size_t off_map = ((size_t)nbins * 8 + (HG ? 0 : (size_t)G * nbins * 4) + 7) & ~size_t(7);
     uint64_t* lmap = (uint64_t*)(smem + off_map) + (size_t)wave * M;
     uint8_t* llat = (uint8_t*)(smem + off_map + (size_t)G * M * 8) + (size_t)wave * N;
     uint64_t* lrow = (uint64_t*)(smem + off_map + (size_t)G * M * 8) + (size_t)wave * L * wpr;
-    // site -> map entry: the site itself when every site has one, else site mod 4096
-    auto ent = [&](int site) { return WIDE ? (site & (kWaveMapMax - 1)) : site; };
+    auto ent = [&](int site) { return (int)((uint32_t)site & mmask); };
     // the walker's counts relative to an offset of its own (a per-walker constant
     // cancels from every decision), chosen and checked as in sweep_tile
     uint64_t cw = 0;
@@ -631,6 +636,20 @@ __device__ void sweep_wave(const Inst& I, const Tile& tile, char* smem)
         };
         classify(0);
 
+        // flips decided but not yet applied to the lattice (d = 0 moves and
+        // accepted moves); they are applied together before the lattice is read
+        // again (a re-evaluation, the next chunk)
+        uint64_t pend = 0;
+        auto apply = [&]() {
+            if (pend) {
+                if (__builtin_amdgcn_inverse_ballot_w64(pend)) {
+                    if (MODEL == 0) atomicXor((unsigned long long*)fword, fbit);
+                    else llat[site] = (uint8_t)nv;
+                }
+                pend = 0;
+            }
+        };
+
         // the run loop; it leaves at the end of the chunk, and to move the
         // register window when a move brings the walker within four bins of its
         // edge (then it continues at attempt i)
@@ -671,17 +690,14 @@ __device__ void sweep_wave(const Inst& I, const Tile& tile, char* smem)
             }
             // attempts i..js-1 were rejected or moved within the bin; the d = 0
             // moves among them and an accepted move at js flip
-            const uint64_t flips = (zall & run & below) | mv;
-            if (flips && __builtin_amdgcn_inverse_ballot_w64(flips)) {
-                if (MODEL == 0) atomicXor((unsigned long long*)fword, fbit);
-                else llat[site] = (uint8_t)nv;
-            }
-            if (mv) {
+            pend |= (zall & run & below) | mv;
+            if (__builtin_expect(mv != 0, 1)) {
                 const int js = (int)__builtin_ctzll(mv);
                 // the old bin after attempts up to js - 1 is t at lane js; the
                 // differences below are exact (multiples of 2^-k, small)
-                const double jsinc = rld(t, js) - B;      // js incv
-                if (lane == idx) gl = B + jsinc;
+                const double tjs = rld(t, js);
+                const double jsinc = tjs - B;             // js incv
+                if (lane == idx) gl = tjs;
                 idx += __builtin_amdgcn_readlane(d, js);
                 stale |= rl64(qm, js);
                 // the new bin's entry lacks attempt js's update, so B = entry - js incv
@@ -701,10 +717,12 @@ __device__ void sweep_wave(const Inst& I, const Tile& tile, char* smem)
             } else {
                 if (!stop) break;
                 i = (int)__builtin_ctzll(stop);           // attempt i is out of date
+                apply();
                 evaluate();
                 classify(i);
             }
         }
+        apply();
         B += (double)n * incv;
     }
     if (lane == idx) gl = B;
@@ -764,22 +782,20 @@ __global__ void __launch_bounds__(512) k_sweep_wave(const Inst* __restrict__ ins
     const Tile tile = tiles[blockIdx.x];
     const Inst& I = insts[tile.inst];
     if (I.ctr->all_done) return;
-    const bool wide = I.N > kWaveMapMax;
+    const bool wide = I.wpr > 1;
     if (I.hglobal) {
         if (I.model == 0) {
             if (wide) sweep_wave<0, true, true>(I, tile, smem);
             else sweep_wave<0, false, true>(I, tile, smem);
         } else {
-            if (wide) sweep_wave<1, true, true>(I, tile, smem);
-            else sweep_wave<1, false, true>(I, tile, smem);
+            sweep_wave<1, false, true>(I, tile, smem);
         }
     } else {
         if (I.model == 0) {
             if (wide) sweep_wave<0, true, false>(I, tile, smem);
             else sweep_wave<0, false, false>(I, tile, smem);
         } else {
-            if (wide) sweep_wave<1, true, false>(I, tile, smem);
-            else sweep_wave<1, false, false>(I, tile, smem);
+            sweep_wave<1, false, false>(I, tile, smem);
         }
     }
 }

@@ -116,28 +116,36 @@ SMALL = [
 
 
 def _tune(rw, kind, wpb=0, graph=0, poll=8, placement="auto"):
-    persistent = 0
+    persistent = map_log2 = 0
     if kind == "wave-device":
         kind, placement = "wave", "device"
+    if kind == "wave-map64":
+        kind, map_log2 = "wave", 6
     if kind == "lane-persist":
         kind, persistent = "lane", 1
-    return rw.make_tune(kind, wpb, graph, poll, table_placement=placement, persistent=persistent)
+    return rw.make_tune(kind, wpb, graph, poll, table_placement=placement, persistent=persistent,
+                        map_log2=map_log2)
 
 
-@pytest.mark.parametrize("kind", ["lane", "lane-persist", "wave", "wave-device"])
+@pytest.mark.parametrize("kind", ["lane", "lane-persist", "wave", "wave-device", "wave-map64"])
 @pytest.mark.parametrize("kw", SMALL, ids=lambda kw: f"{kw['model']}-L{kw['L']}-h{kw['n_windows']}-m{kw['m']}"
                                                    f"{'-' + kw['flat_rule'] if 'flat_rule' in kw else ''}"
                                                    f"{'-windows' if 'windows' in kw else ''}")
 def test_lockstep_small(rw, kw, kind):
     """Lane sweep (one block per tile, or a persistent grid over a tile queue), wave
-    sweep with the counts in LDS, and wave sweep with the counts read from device
-    memory: each bit-identical to the oracle."""
+    sweep with the counts in LDS, with the counts read from device memory, and with
+    a site map of 64 entries (sites equal modulo 64 share one: extra re-evaluations
+    on every lattice above 8 x 8): each bit-identical to the oracle."""
     steps = 40 if kw["X"] > 1 else 3000
     gpu, _, _ = _lockstep(rw, kw, steps, tune=_tune(rw, kind), every=1 if kw["X"] > 1 else 500)
     info = gpu.info()
     assert info["sweep_kind"] == kind.split("-")[0]          # every lattice here fits either variant
     if kind == "wave-device":
         assert info["table_placement"] == "device"
+    if kind == "wave-map64":
+        assert info["map_entries"] == min(kw["L"] ** 2, 64)
+    elif kind.startswith("wave"):
+        assert info["map_entries"] == min(kw["L"] ** 2, 4096)    # small batches: the full map
 
 
 def test_ising_L8_full_run_bitwise(rw):
@@ -309,6 +317,20 @@ def test_full_size_merges_to_done(rw, kw, kind):
     gpu, orc, done = _lockstep(rw, kw, 12, tune=_tune(rw, kind))
     assert done and orc.t == 10
     assert list(gpu.stats()["k"]) == [10] * kw["n_windows"]
+
+
+@pytest.mark.parametrize("name", ["potts64", "ising128"])
+def test_resident_site_map_full_size(rw, name):
+    """The larger targets (10-state Potts L=64, 32 windows x 128 walkers; Ising
+    L=128, 32 x 64) with the library's own choice of placement and site map: a map
+    below the 4096-entry cap, so that every walker is resident at once, and with it
+    sites sharing map entries.  Three intervals bit-exact to the oracle."""
+    from paper_1407_5140_amd import workloads as W
+    kw = W.single(name)
+    gpu, orc, _ = _lockstep(rw, kw, 3)
+    info = gpu.info()
+    print(name, info, flush=True)
+    assert info["sweep_kind"] == "wave" and info["map_entries"] < 4096
 
 
 @pytest.mark.parametrize("kw", [
