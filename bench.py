@@ -53,7 +53,8 @@ LABELS = {
 # rocprofv3 summaries holding the HBM byte counters of a workload's sweep kernel
 PROFILES = {"ising64": "k_sweep_wave_ising_L64.txt", "potts32": "k_sweep_wave_potts_q10_L32.txt",
             "batch64": "k_sweep_persist_k_rng_batch64_lane_lds53.txt",
-            "ising128": "k_sweep_wave_device_ising_L128.txt"}
+            "ising128": "k_sweep_wave_device_ising_L128.txt",
+            "potts64": "k_sweep_wave_device_potts_q10_L64.txt"}
 KERNEL_SOURCES = ("paper_1407_5140_amd/csrc/rewl_kernels.hip", "paper_1407_5140_amd/csrc/rewl_device.hpp")
 
 
