@@ -963,6 +963,7 @@ def main(argv=None):
     if args.workload == "ising64" and not args.no_extras and not args.autotune:
         out["batch64"] = batch_line(rw)
         out["time_to_converge"] = ising8_converge(rw)
+        out["warm_vs_plain"] = warm_line(rw)
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on the host cores", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(kws, args.cpu_budget)
@@ -1016,6 +1017,51 @@ def ising8_converge(rw, seeds=(1, 2, 3)) -> dict:
             "seconds": [r["seconds"] for r in res], "intervals": [r["intervals"] for r in res],
             "converged": [r["converged"] for r in res],
             "eps_mean": [r.get("eps_mean") for r in res], "eps_max": [r.get("eps_max") for r in res]}
+
+
+def warm_line(rw, seeds=(1, 2, 3), k0: int = 8) -> dict:
+    """The network's warm start against plain REWL, small enough for every bench run:
+    the network is trained on REWL's own results (4 windows, 8 walkers, ln f -> 2^-13)
+    for Ising L 8-16 and Potts q 4/8/10 L 8-12, produced here; the target is 10-state
+    Potts L=16 (4 windows x 8 walkers, X = 2000) to ln f = 2^-13, three seeds warm (from
+    2^-k0) and three plain (from 1), each group in its own handle.  Intervals are exactly
+    reproducible (counter-based random numbers); seconds are the group's wall time."""
+    from paper_1407_5140_amd import warm as Wm
+    types = [("ising", 2, 8), ("ising", 2, 12), ("ising", 2, 16), ("potts", 4, 8), ("potts", 4, 12),
+             ("potts", 8, 8), ("potts", 8, 12), ("potts", 10, 8), ("potts", 10, 12)]
+    t0 = time.perf_counter()
+    kws = Wm.training_workload(types, m=8, kfinal=13, X=2000, seed0=500)
+    for kw in kws:
+        kw["n_windows"] = 4
+    g, res = Wm.run_to_convergence(kws, 120.0)
+    ok = [r["converged"] for r in res]
+    x, t = Wm.training_rows(g, kws, ok)
+    g.close()
+    net, info = Wm.train(x, t, steps=1500, batch=1024, lr=1e-3, seed=1)
+    t_train = time.perf_counter() - t0
+    base = dict(model="potts", q=10, L=16, n_windows=4, m=8, kfinal=13, X=2000)
+    table = Wm.warm_table(net, base)
+    net.close()
+    out = {"workload": "10-state Potts L=16 periodic, 4 windows o=3/4, 8 walkers/window, X=2000, "
+                       f"ln f 1 (plain) or 2^-{k0} (warm) -> 2^-13",
+           "train": {"instances": len(kws), "converged": int(sum(ok)), "rows": int(len(t)),
+                     "seconds_with_training": t_train, "rms": info["rms"]}}
+    for mode in ("plain", "warm"):
+        kk = [dict(base, seed=sd, k0=k0 if mode == "warm" else 0) for sd in seeds]
+        ts = time.perf_counter()
+        gg, rr = Wm.run_to_convergence(kk, 120.0, warm_tables=[table] * len(kk) if mode == "warm" else None,
+                                       poll=10)
+        wall = time.perf_counter() - ts
+        gg.close()
+        out[mode] = {"intervals": [r["intervals"] for r in rr], "converged": [r["converged"] for r in rr],
+                     "seconds": wall}
+    if all(out["plain"]["converged"]) and all(out["warm"]["converged"]):
+        out["intervals_plain_over_warm"] = float(np.median(out["plain"]["intervals"]) /
+                                                 np.median(out["warm"]["intervals"]))
+        out["seconds_plain_over_warm"] = out["plain"]["seconds"] / out["warm"]["seconds"]
+    print(f"[bench] warm vs plain: {out.get('intervals_plain_over_warm')} x fewer intervals, "
+          f"{out.get('seconds_plain_over_warm')} x less time", file=sys.stderr, flush=True)
+    return out
 
 
 if __name__ == "__main__":
