@@ -526,8 +526,11 @@ static rewl_status create_impl(const rewl_config* cfgs, int32_t n, void* hip_str
         // 3.50 ms per 10^4 attempts); with tens of thousands of walkers the lane
         // variant's width wins (the 64-instance batch).
         // any lattice, as long as one walker's wave tables fit (the site map is bounded)
+        // (with the smallest site map the library would take, or the one asked for)
         const bool wave_ok =
-            wave_lds_bytes(c.model, c.L, hi.WB, 1, true, wave_map_entries(hi.N, 9)) <= (size_t)lds_limit;
+            wave_lds_bytes(c.model, c.L, hi.WB, 1, true,
+                           wave_map_entries(hi.N, H->tune.map_log2 > 0 ? H->tune.map_log2 : 9)) <=
+            (size_t)lds_limit;
         int64_t total_walkers = 0;
         for (int u = 0; u < n; ++u) total_walkers += (int64_t)cfgs[u].n_windows * cfgs[u].walkers_per_window;
         hi.kind = REWL_SWEEP_LANE;
@@ -565,23 +568,27 @@ static rewl_status create_impl(const rewl_config* cfgs, int32_t n, void* hip_str
                     const int mn = wave_map_entries(hi.N, lg);
                     if (maps.empty() || mn < maps.back()) maps.push_back(mn);
                 }
-            for (int mapn : maps)
-                for (bool hg : places) {
-                    int G = G0;
-                    while (G > 1 && wave_lds_bytes(c.model, c.L, hi.WB, G, hg, mapn) > (size_t)lds_limit) G /= 2;
-                    const size_t lds = wave_lds_bytes(c.model, c.L, hi.WB, G, hg, mapn);
-                    if (lds > (size_t)lds_limit) continue;
-                    const int64_t per_cu = std::min<int64_t>((int64_t)lds_limit / (int64_t)lds, wave_cap / G);
-                    const int64_t resident = std::max<int64_t>(1, per_cu * G * n_cu);
-                    const int64_t rounds = (hi.S + resident - 1) / resident;
-                    // candidates come largest map first, LDS before device memory
-                    if (rounds < best.rounds) best = Choice{G, mapn, hg, lds, rounds};
-                }
-            if (best.G == 0) {
-                // one walker's tables exceed the LDS: reported below
-                best = Choice{1, wave_map_entries(hi.N, 0), true, wave_lds_bytes(c.model, c.L, hi.WB, 1, true,
-                                                                                  wave_map_entries(hi.N, 0)), 0};
-            }
+            auto search = [&](const std::vector<bool>& pl) {
+                for (int mapn : maps)
+                    for (bool hg : pl) {
+                        int G = G0;
+                        while (G > 1 && wave_lds_bytes(c.model, c.L, hi.WB, G, hg, mapn) > (size_t)lds_limit)
+                            G /= 2;
+                        const size_t lds = wave_lds_bytes(c.model, c.L, hi.WB, G, hg, mapn);
+                        if (lds > (size_t)lds_limit) continue;
+                        const int64_t per_cu =
+                            std::max<int64_t>(1, std::min<int64_t>((int64_t)lds_limit / (int64_t)lds, wave_cap / G));
+                        const int64_t resident = per_cu * G * n_cu;
+                        const int64_t rounds = (hi.S + resident - 1) / resident;
+                        // candidates come largest map first, LDS before device memory
+                        if (rounds < best.rounds) best = Choice{G, mapn, hg, lds, rounds};
+                    }
+            };
+            search(places);
+            // counts asked for in LDS that do not fit there go to device memory
+            if (best.G == 0) search({true});
+            if (best.G == 0)
+                return bail(fail(REWL_E_INVALID, "instance " + std::to_string(i) + ": one walker's tables exceed LDS"));
             hi.placement = best.hg ? REWL_TABLE_DEVICE : REWL_TABLE_LDS;
             hi.wpb = best.G;
             hi.mapn = best.mapn;

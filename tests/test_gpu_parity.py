@@ -319,6 +319,18 @@ def test_full_size_merges_to_done(rw, kw, kind):
     assert list(gpu.stats()["k"]) == [10] * kw["n_windows"]
 
 
+def test_lds_counts_that_do_not_fit_go_to_device_memory(rw):
+    """10-state Potts L=90 in one window of 16 201 bins: the base table (130 KB) leaves
+    no room for an LDS copy of the counts, so counts asked for in LDS are kept in
+    device memory, with the largest site map that fits (2 048 entries for 8 100
+    sites); bit-exact to the oracle."""
+    kw = dict(model="potts", q=10, L=90, n_windows=1, m=2, kfinal=8, X=2000, seed=53)
+    gpu, _, _ = _lockstep(rw, kw, 5, tune=_tune(rw, "wave", placement="lds"))
+    info = gpu.info()
+    assert info["sweep_kind"] == "wave" and info["table_placement"] == "device"
+    assert info["map_entries"] == 2048
+
+
 @pytest.mark.parametrize("name", ["potts64", "ising128"])
 def test_resident_site_map_full_size(rw, name):
     """The larger targets (10-state Potts L=64, 32 windows x 128 walkers; Ising
