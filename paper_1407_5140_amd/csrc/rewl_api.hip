@@ -518,15 +518,15 @@ static rewl_status create_impl(const rewl_config* cfgs, int32_t n, void* hip_str
         hi.nreach.assign(hi.h, 0);
         for (int a = 0; a < hi.h; ++a)
             for (int b = hi.lo[a]; b <= hi.hi[a]; ++b) hi.nreach[a] += hi.mask[b];
-        // sweep variant.  The lane variant serves a wave of walkers with ~70
-        // instructions per attempt; the wave variant serves one walker with ~34
-        // (chunked evaluation and runs).  With few walkers per SIMD the chain
-        // latency sets the rate and the wave variant wins (measured: Ising L=64
-        // 1024 walkers 1.39 vs 2.66 ms, Potts q=10 L=32 4096 walkers 1.78 vs
-        // 3.50 ms per 10^4 attempts); with tens of thousands of walkers the lane
-        // variant's width wins (the 64-instance batch).
-        // any lattice, as long as one walker's wave tables fit (the site map is bounded)
-        // (with the smallest site map the library would take, or the one asked for)
+        // sweep variant.  The lane variant serves a wave of walkers with ~74
+        // instructions per wave-attempt; the wave variant serves one walker with
+        // ~27 per attempt (chunked evaluation and runs).  With few walkers per
+        // SIMD the chain latency sets the rate and the wave variant wins (about
+        // 2.4x on Ising L=64 with 1024 walkers and on Potts q=10 L=32 with 4096);
+        // with tens of thousands of walkers the lane variant's width wins (the
+        // 64-instance batch).  The wave variant takes any lattice whose walker
+        // tables fit the LDS with the smallest site map the choice below may
+        // take, or with the one asked for.
         const bool wave_ok =
             wave_lds_bytes(c.model, c.L, hi.WB, 1, true,
                            wave_map_entries(hi.N, H->tune.map_log2 > 0 ? H->tune.map_log2 : 9)) <=
