@@ -40,22 +40,34 @@ __global__ void __launch_bounds__(256) k_rng(const Inst* __restrict__ insts,
     const uint32_t nthreads = (uint32_t)(block_start[lo + 1] - block_start[lo]) * blockDim.x;
     const uint64_t T0 = (uint64_t)I.ctr->t * (uint64_t)X;
     const uint32_t N = I.N, L = I.L, qm1 = I.q - 1;
-    for (uint32_t e = (uint32_t)(b - block_start[lo]) * blockDim.x + threadIdx.x; e < n; e += nthreads) {
-        const uint32_t slot = e / X;
-        const uint32_t j = e - slot * X;
+    const float rL = 1.0f / (float)L;
+    // element e = slot X + j, walked with stride nthreads = sq X + sr: the
+    // division happens once per thread, then slot and j advance by adds
+    const uint32_t e0 = (uint32_t)(b - block_start[lo]) * blockDim.x + threadIdx.x;
+    const uint32_t sq = nthreads / X, sr = nthreads - sq * X;
+    uint32_t slot = e0 / X, j = e0 - slot * X;
+    for (uint64_t e = e0; e < n; e += nthreads) {
         const u32x4 x = draw(I.k0, I.k1, T0 + j, slot, kTagFlip);
         const uint32_t site = (uint32_t)(((uint64_t)x.x * N) >> 32);
-        const uint32_t row = site / L, col = site - row * L;
+        // row = site / L: site < 2^24 is exact in FP32, the product's rounding
+        // puts the estimate at most one off, corrected below
+        uint32_t row = (uint32_t)((float)site * rL);
+        int32_t col = (int32_t)site - (int32_t)(row * L);
+        if (col < 0) { --row; col += (int32_t)L; }
+        else if (col >= (int32_t)L) { ++row; col -= (int32_t)L; }
         uint32_t pack;
         if (I.model) {
-            pack = row | (col << 8) | ((uint32_t)(((uint64_t)x.y * qm1) >> 32) << 16);
+            pack = row | ((uint32_t)col << 8) | ((uint32_t)(((uint64_t)x.y * qm1) >> 32) << 16);
         } else {
             const uint32_t ru = row == 0 ? L - 1 : row - 1, rd = row == L - 1 ? 0 : row + 1;
-            pack = row | (col << 8) | (ru << 16) | (rd << 24);
+            pack = row | ((uint32_t)col << 8) | (ru << 16) | (rd << 24);
         }
         const size_t idx = (size_t)slot * XP + j;
         I.rpack[idx] = pack;
         I.rv[idx] = threshold_of(u53_of(x), I.band);
+        slot += sq;
+        j += sr;
+        if (j >= X) { j -= X; ++slot; }
     }
 }
 
