@@ -582,32 +582,41 @@ def headline_study(rw, args) -> dict:
 
 
 def target_study(rw, args) -> dict:
-    """Warm start against plain REWL on a large target at equal GPU time.
+    """Warm start against plain REWL on a large target.
 
     The network is trained on REWL's own results (ln f -> 2^-16) for every type of
-    the 64-instance batch with L <= 48, produced in this run.  The target then runs
-    once plain (ln f from 1) and once per warm k0 (the network's table, ln f from
-    2^-k0), all as instances of one handle, so that every sweep launch covers all of
-    them and they share one clock.  Reported: per-window k of every instance at
-    regular times, and the first time each instance had every window at k >= K."""
+    the 64-instance batch with L <= 48, produced in this run (skipped when every
+    instance is plain).  The target then runs once per entry of --ts-k0: 0 is plain
+    (ln f from 1), k0 > 0 the network's table with ln f from 2^-k0, -1 the k0 the
+    table's error suggests.  All of them are instances of one handle, so every sweep
+    launch covers all of them and they share one clock (a single entry has the GPU
+    to itself).  Reported: per-window k of every instance at regular times, the
+    first time each instance had every window at k >= K, and for converged Ising
+    instances the error against the exact DOS."""
     from paper_1407_5140_amd import warm as Wm
     log = lambda m: print(f"[target] {m}", file=sys.stderr, flush=True)
-    t0 = time.perf_counter()
-    kws = Wm.training_workload(Wm.TRAIN_TYPES, m=32, kfinal=16)
-    g, res = Wm.run_to_convergence(kws, args.max_seconds, log=log)
-    okr = [r["converged"] for r in res]
-    x, t = Wm.training_rows(g, kws, okr)
-    g.close()
-    t_data = time.perf_counter() - t0
-    net, info = Wm.train(x, t, steps=args.mlp_steps, batch=4096, lr=1e-3)
-    log(f"training: {sum(okr)}/{len(kws)} instances, {len(t)} rows, {t_data:.1f} s; network {info}")
     target = dict(workload(args.ts_target)[0], seed=args.ts_seed)
     if args.windows == "tilted":
         target["windows"] = tilted_windows(rw, target)
-    tab = Wm.warm_table(net, target)
-    net.close()
-    k0s = [0] + [Wm.suggest_k0(info["rms"], target["L"] ** 2) if int(v) < 0 else int(v)
-                 for v in args.ts_k0.split(",")]
+    asked = [int(v) for v in args.ts_k0.split(",")]
+    out = {"mode": "warm start vs plain on a large target, one handle"}
+    tab, info = None, None
+    if any(v != 0 for v in asked):
+        t0 = time.perf_counter()
+        kws = Wm.training_workload(Wm.TRAIN_TYPES, m=32, kfinal=16)
+        g, res = Wm.run_to_convergence(kws, args.max_seconds, log=log)
+        okr = [r["converged"] for r in res]
+        x, t = Wm.training_rows(g, kws, okr)
+        g.close()
+        t_data = time.perf_counter() - t0
+        net, info = Wm.train(x, t, steps=args.mlp_steps, batch=4096, lr=1e-3)
+        log(f"training: {sum(okr)}/{len(kws)} instances, {len(t)} rows, {t_data:.1f} s; network {info}")
+        tab = Wm.warm_table(net, target)
+        net.close()
+        out["train"] = {"types": Wm.TRAIN_TYPES, "converged": int(sum(okr)), "rows": int(len(t)),
+                        "seconds": t_data}
+        out["network"] = info
+    k0s = [v if v >= 0 else Wm.suggest_k0(info["rms"], target["L"] ** 2) for v in asked]
     cfgs = [rw.make_config(**dict(target, k0=k0)) for k0 in k0s]
     gg = rw.Rewl(cfgs, tune=rw.make_tune(autotune=1, use_graph=1, poll_every=1 << 20))
     for i, k0 in enumerate(k0s):
@@ -623,32 +632,43 @@ def target_study(rw, args) -> dict:
         now = time.perf_counter() - ts
         sts = [gg.stats(i) for i in range(len(k0s))]
         for i, st in enumerate(sts):
-            for K in range(0, min(st["k"]) + 1):
+            for K in range(0, int(min(st["k"])) + 1):
                 reached[i].setdefault(K, (now, st["intervals"]))
         if now - last >= args.ts_sample or all_done or now > args.ts_seconds:
             samples.append({"seconds": now, "intervals": sts[0]["intervals"],
                             "k": [[int(v) for v in st["k"]] for st in sts],
                             "round_trips": [int(st["round_trips_total"]) for st in sts]})
-            log(f"{now:.0f} s, {sts[0]['intervals']} intervals: min k {[min(st['k']) for st in sts]}, "
+            log(f"{now:.0f} s, {sts[0]['intervals']} intervals: min k {[int(min(st['k'])) for st in sts]}, "
                 f"mean k {[round(float(np.mean(st['k'])), 2) for st in sts]}, windows done "
                 f"{[int(st['windows_done']) for st in sts]}/{h}")
             last = now
         if all_done or now > args.ts_seconds:
             break
+    names = ["plain" if k0 == 0 else f"warm k0={k0}" for k0 in k0s]
+    kf = target["kfinal"]
+    ex = exact_ln_g(target)
+    runs = []
+    for i in range(len(k0s)):
+        r = {"instance": names[i], "converged": kf in reached[i],
+             "seconds": reached[i][kf][0] if kf in reached[i] else None,
+             "intervals": reached[i][kf][1] if kf in reached[i] else None}
+        if ex is not None and r["converged"]:
+            lng, _ = gg.concat(i)
+            ok = np.isfinite(ex)
+            e = np.abs(lng[ok] - ex[ok]) / np.abs(ex[ok])
+            big = ex[ok] > 10
+            r.update(eps_max=float(e.max()), eps_mean=float(e.mean()),
+                     abs_err_max_lng_above_10=float(np.abs(lng[ok] - ex[ok])[big].max()))
+        runs.append(r)
+        log(f"{names[i]}: {r}")
     gg.close()
-    names = ["plain"] + [f"warm k0={k0}" for k0 in k0s[1:]]
     levels = sorted(set().union(*[r.keys() for r in reached]))
     first = {str(K): [reached[i].get(K, (None, None))[0] for i in range(len(k0s))] for K in levels}
-    # plain's time to reach K on every window over each warm instance's
-    ratio = {names[i]: {K: v[0] / v[i] for K, v in first.items() if v[0] is not None and v[i]}
-             for i in range(1, len(k0s))}
-    return {"mode": "warm start vs plain at equal GPU time, one handle",
-            "workload": f"{LABELS.get(args.ts_target, args.ts_target)}; windows {args.windows}; "
-                        f"ln f 1 (plain) or 2^-k0 (warm) -> 2^-{target['kfinal']}; seed {args.ts_seed}",
-            "instances": names, "k0": k0s, "seconds_limit": args.ts_seconds,
-            "train": {"types": Wm.TRAIN_TYPES, "converged": int(sum(okr)), "rows": int(len(t)),
-                      "seconds": t_data}, "network": info,
-            "first_all_windows_at_k": first, "plain_over_warm_at_k": ratio, "samples": samples}
+    out.update({"workload": f"{LABELS.get(args.ts_target, args.ts_target)}; windows {args.windows}; "
+                            f"ln f 1 (plain) or 2^-k0 (warm) -> 2^-{kf}; seed {args.ts_seed}",
+                "instances": names, "k0": k0s, "seconds_limit": args.ts_seconds, "runs": runs,
+                "first_all_windows_at_k": first, "samples": samples})
+    return out
 
 
 def accuracy_study(rw, args) -> dict:
@@ -792,7 +812,8 @@ def main(argv=None):
     ap.add_argument("--target-study", action="store_true",
                     help="warm start against plain on a large target at equal GPU time")
     ap.add_argument("--ts-target", default="potts64")
-    ap.add_argument("--ts-k0", default="-1,10", help="warm k0 values (-1: from the network's error)")
+    ap.add_argument("--ts-k0", default="0,-1,10",
+                    help="one instance per value: 0 plain, k0 > 0 warm from 2^-k0, -1 k0 from the network's error")
     ap.add_argument("--ts-seconds", type=float, default=900.0)
     ap.add_argument("--ts-sample", type=float, default=30.0)
     ap.add_argument("--ts-seed", type=int, default=1)

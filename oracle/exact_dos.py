@@ -312,8 +312,14 @@ def _kaufman_mod(L: int, p: int, n: int):
     return coef * scale % p
 
 
-def kaufman_ising(L: int) -> list[int]:
-    """Exact integer DOS of the L x L periodic Ising model (L even), by bin."""
+def _kaufman_residues(args):
+    L, p, n, N = args
+    return [int(v) for v in _kaufman_mod(L, p, n)[: N + 1]]
+
+
+def kaufman_ising(L: int, processes: int = 1) -> list[int]:
+    """Exact integer DOS of the L x L periodic Ising model (L even), by bin.
+    processes > 1 evaluates the primes in a process pool (same result)."""
     if L % 2 or L < 2:
         raise ValueError("even L required")
     N = L * L
@@ -323,7 +329,13 @@ def kaufman_ising(L: int) -> list[int]:
     modulus = (2 * n) * (2 * L) // math.gcd(2 * n, 2 * L)
     count = (N + 8) // 29 + 2
     primes = _primes(count, 1 << 30, modulus)
-    res = [[int(v) for v in _kaufman_mod(L, p, n)[: N + 1]] for p in primes]
+    jobs = [(L, p, n, N) for p in primes]
+    if processes > 1:
+        import multiprocessing as mp
+        with mp.Pool(processes) as pool:
+            res = pool.map(_kaufman_residues, jobs)
+    else:
+        res = [_kaufman_residues(j) for j in jobs]
     g = _crt(res, primes)
     if sum(g) != 2 ** N:
         raise AssertionError("sum of g differs from 2^N")

@@ -132,7 +132,7 @@ def test_brute_force_small_table():
     assert g[1] == 0 and g[15] == 0
 
 
-@pytest.mark.parametrize("L", [16, 24, 32, 48, 64])
+@pytest.mark.parametrize("L", [16, 24, 32, 48, 64, 128])
 def test_ising_exact_invariants(golden, L):
     lg = golden.lng(f"ising_L{L}_lng.txt")
     N = L * L
