@@ -36,7 +36,7 @@ def main(argv):
         write_counts(f"{model}_q{q}_L{L}_counts.txt", g,
                      f"{model} q={q} L={L} periodic: exact counts by enumeration of all states")
     for model, q, L in [("ising", 2, 6), ("ising", 2, 8), ("potts", 3, 4), ("potts", 4, 4),
-                        ("potts", 3, 5)]:
+                        ("potts", 3, 5), ("potts", 10, 3)]:
         g = X.transfer_matrix(model, q, L)
         write_counts(f"{model}_q{q}_L{L}_counts.txt", g,
                      f"{model} q={q} L={L} periodic: exact counts by row transfer matrix (mod-p + CRT)")

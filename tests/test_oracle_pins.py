@@ -149,7 +149,8 @@ def test_ising_exact_invariants(golden, L):
 
 
 @pytest.mark.parametrize("name,q,L", [("potts_q3_L3_counts.txt", 3, 3), ("potts_q3_L4_counts.txt", 3, 4),
-                                      ("potts_q4_L4_counts.txt", 4, 4), ("potts_q3_L5_counts.txt", 3, 5)])
+                                      ("potts_q4_L4_counts.txt", 4, 4), ("potts_q3_L5_counts.txt", 3, 5),
+                                      ("potts_q10_L3_counts.txt", 10, 3)])
 def test_potts_exact_closed_forms(golden, name, q, L):
     g = golden.counts(name)
     N = L * L
@@ -365,6 +366,31 @@ def test_rewl_converges_to_exact_potts_q3_L4(golden):
     assert sim.run(100000)
     err = _concat_error(sim, exact)
     assert err.max() < 0.12
+
+
+def test_potts_q10_L3_six_broken_bonds(golden):
+    """10-state Potts L=3: six broken bonds come from a flipped domino (2N q(q-1)) or,
+    on the 3 x 3 torus only, from a whole row or column taking one other state
+    (2L q(q-1)); the transfer-matrix table must hold both and nothing else."""
+    g = golden.counts("potts_q10_L3_counts.txt")
+    q, L, N = 10, 3, 9
+    assert g[6] == 2 * N * q * (q - 1) + 2 * L * q * (q - 1)
+    assert g[1] == g[2] == g[3] == g[5] == 0
+
+
+def test_rewl_converges_to_exact_potts_q10_L3(golden):
+    """The paper's 10-state Potts model on the smallest lattice with an exact DOS
+    (transfer matrix): REWL, 2 windows x 8 walkers, ln f -> 2^-18, joined result
+    within 0.08 of the exact ln g at every level that occurs."""
+    g = golden.counts("potts_q10_L3_counts.txt")
+    exact = X.ln_g(g)
+    mask = (np.array(g) > 0).astype(np.uint8)
+    c = O.make_config("potts", q=10, L=3, n_windows=2, m=8, kfinal=18, X=5000, seed=3)
+    sim = O.Sim(c, mask=mask)
+    assert sim.run(100000)
+    out, _ = O.concat(c, mask, sim.pieces())
+    ok = mask > 0
+    assert np.abs(out[ok] - exact[ok]).max() < 0.08
 
 
 def test_rewl_brute_force_potts_q3_L3(golden):
