@@ -160,6 +160,20 @@ rewl_status rewl_layout(const rewl_config* cfg, int32_t* n_bins, int32_t* window
  * receive inclusive global bins valid as the config's explicit windows.          */
 rewl_status rewl_balanced_layout(const rewl_config* cfg, const double* rho, int32_t* lo, int32_t* hi);
 
+/* Pure host: the WAVE sweep's plan for an instance of cfg alone, as the library
+ * makes it at creation from the device's LDS bytes per block, CU count and the
+ * waves of the sweep kernel a CU holds (hipDeviceGetAttribute / the occupancy
+ * API): walkers per block, count placement (REWL_TABLE_LDS / _DEVICE), site-map
+ * entries per walker and LDS bytes per block.  The plan keeps the most walkers
+ * resident at once (fewest rounds of blocks over the CUs); on a tie the larger
+ * map, then LDS; counts asked for in LDS that do not fit go to device memory.
+ * tune may be NULL (library choices); its walkers_per_block, table_placement and
+ * map_log2 apply.  Returns REWL_E_INVALID for a bad argument or when one
+ * walker's tables do not fit.  Output pointers may be NULL.                       */
+rewl_status rewl_wave_plan(const rewl_config* cfg, const rewl_tune* tune, int32_t lds_per_block, int32_t n_cu,
+                           int32_t waves_per_cu, int32_t* walkers_per_block, int32_t* placement,
+                           int32_t* map_entries, size_t* lds_bytes);
+
 /* Pure host: a difficulty density for rewl_balanced_layout from a model of the
  * single-spin-flip walk near the ground levels, where a walker spends most
  * attempts on rejected moves (the slow end windows that Sec. V proposes to

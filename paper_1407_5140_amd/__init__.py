@@ -106,6 +106,8 @@ _sigs = {
     "rewl_restore": ([_vp, _vp, ctypes.c_size_t], ctypes.c_int),
     "rewl_destroy": ([_vp], None),
     "rewl_info": ([_vp, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
+    "rewl_wave_plan": ([_P(rewl_config), _P(rewl_tune), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                        _vp, _vp, _vp, _vp], ctypes.c_int),
     "rewl_get_tune": ([_vp, _P(rewl_tune)], ctypes.c_int),
     "rewl_probe_accept": ([_vp, _vp, ctypes.c_int32, _vp], ctypes.c_int),
     "rewl_probe_philox": ([_vp, ctypes.c_int32, _vp], ctypes.c_int),
@@ -341,6 +343,18 @@ def rewl_info(h, instance: int = 0) -> dict:
     return dict(n_instances=n.value, sweep_kind={1: "lane", 2: "wave"}[kind.value],
                 walkers_per_block=w.value, lds_bytes=lds.value,
                 table_placement={1: "lds", 2: "device"}[pl.value], map_entries=mp.value)
+
+
+def rewl_wave_plan(cfg: rewl_config, tune: rewl_tune | None = None, lds_per_block: int = 163840,
+                   n_cu: int = 256, waves_per_cu: int = 16) -> dict:
+    """Pure host: the wave sweep's plan for one instance (defaults: MI355X's 160 KiB of
+    LDS, 256 CUs and 16 waves of the sweep kernel per CU)."""
+    g, pl, mp, lds = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_size_t()
+    _check(_lib.rewl_wave_plan(ctypes.byref(cfg), ctypes.byref(tune) if tune is not None else None,
+                               lds_per_block, n_cu, waves_per_cu, ctypes.byref(g), ctypes.byref(pl),
+                               ctypes.byref(mp), ctypes.byref(lds)), "rewl_wave_plan")
+    return dict(walkers_per_block=g.value, table_placement={1: "lds", 2: "device"}[pl.value],
+                map_entries=mp.value, lds_bytes=lds.value)
 
 
 def rewl_get_tune(h) -> dict:

@@ -196,6 +196,55 @@ struct rewl_handle {
 
 namespace {
 
+// The wave sweep's plan for one instance: walkers per block, count placement and
+// site-map size.  Among the candidate maps (largest first) and placements (LDS
+// first), the one that keeps the most of the instance's S walkers resident at
+// once (fewest rounds of blocks over n_cu CUs, from the LDS per block and the
+// waves a CU holds) wins; on a tie the earlier candidate.  Counts asked for in
+// LDS that do not fit there go to device memory.  False when nothing fits.
+struct WavePlan { int G, mapn; bool hg; size_t lds; };
+
+bool plan_wave(int model, int L, int N, int WB, int m, int64_t S, const rewl_tune& tune, int lds_limit,
+               int n_cu, int wave_cap, WavePlan* out)
+{
+    const int want = tune.walkers_per_block > 0 ? tune.walkers_per_block : 4;
+    int G0 = 1;
+    while (G0 * 2 <= std::min(want, std::min(8, m))) G0 *= 2;
+    std::vector<bool> places;
+    if (tune.table_placement != REWL_TABLE_DEVICE) places.push_back(false);
+    if (tune.table_placement != REWL_TABLE_LDS) places.push_back(true);
+    std::vector<int> maps;
+    if (tune.map_log2 > 0) maps.push_back(wave_map_entries(N, tune.map_log2));
+    else
+        for (int lg = 12; lg >= 9; --lg) {
+            const int mn = wave_map_entries(N, lg);
+            if (maps.empty() || mn < maps.back()) maps.push_back(mn);
+        }
+    WavePlan best{0, 0, false, 0};
+    int64_t best_rounds = INT64_MAX;
+    auto search = [&](const std::vector<bool>& pl) {
+        for (int mapn : maps)
+            for (bool hg : pl) {
+                int G = G0;
+                while (G > 1 && wave_lds_bytes(model, L, WB, G, hg, mapn) > (size_t)lds_limit) G /= 2;
+                const size_t lds = wave_lds_bytes(model, L, WB, G, hg, mapn);
+                if (lds > (size_t)lds_limit) continue;
+                const int64_t per_cu =
+                    std::max<int64_t>(1, std::min<int64_t>((int64_t)lds_limit / (int64_t)lds, wave_cap / G));
+                const int64_t resident = per_cu * G * std::max(n_cu, 1);
+                const int64_t rounds = (S + resident - 1) / resident;
+                if (rounds < best_rounds) {
+                    best_rounds = rounds;
+                    best = WavePlan{G, mapn, hg, lds};
+                }
+            }
+    };
+    search(places);
+    if (best.G == 0) search({true});
+    *out = best;
+    return best.G > 0;
+}
+
 rewl_status enqueue_interval(rewl_handle* H, bool time_it)
 {
     if (time_it) HIP_TRY(hipEventRecord(H->ev[0], H->stream));
@@ -341,6 +390,37 @@ rewl_status rewl_layout(const rewl_config* cfg, int32_t* n_bins, int32_t* window
     }
     if (lo) std::copy(l.begin(), l.end(), lo);
     if (hi) std::copy(u.begin(), u.end(), hi);
+    return REWL_OK;
+}
+
+rewl_status rewl_wave_plan(const rewl_config* cfg, const rewl_tune* tune, int32_t lds_per_block, int32_t n_cu,
+                           int32_t waves_per_cu, int32_t* walkers_per_block, int32_t* placement,
+                           int32_t* map_entries, size_t* lds_bytes)
+{
+    if (!cfg) return fail(REWL_E_INVALID, "null config");
+    rewl_status s = validate(*cfg);
+    if (s != REWL_OK) return s;
+    if (lds_per_block < 1 || n_cu < 1 || waves_per_cu < 1)
+        return fail(REWL_E_INVALID, "lds_per_block, n_cu and waves_per_cu must be positive");
+    rewl_tune t{};
+    if (tune) t = *tune;
+    if (t.table_placement < REWL_TABLE_AUTO || t.table_placement > REWL_TABLE_DEVICE)
+        return fail(REWL_E_INVALID, "table_placement must be REWL_TABLE_AUTO, _LDS or _DEVICE");
+    if (t.map_log2 != 0 && (t.map_log2 < 6 || t.map_log2 > 12))
+        return fail(REWL_E_INVALID, "map_log2 must be 0 (auto) or in [6, 12]");
+    std::vector<int32_t> l, u;
+    layout_of(*cfg, l, u);
+    int WB = 0;
+    for (size_t a = 0; a < l.size(); ++a) WB = std::max(WB, u[a] - l[a] + 1);
+    const int N = cfg->L * cfg->L, m = cfg->walkers_per_window;
+    WavePlan p;
+    if (!plan_wave(cfg->model, cfg->L, N, WB, m, (int64_t)cfg->n_windows * m, t, lds_per_block, n_cu,
+                   waves_per_cu, &p))
+        return fail(REWL_E_INVALID, "one walker's wave tables exceed the LDS per block");
+    if (walkers_per_block) *walkers_per_block = p.G;
+    if (placement) *placement = p.hg ? REWL_TABLE_DEVICE : REWL_TABLE_LDS;
+    if (map_entries) *map_entries = p.mapn;
+    if (lds_bytes) *lds_bytes = p.lds;
     return REWL_OK;
 }
 
@@ -549,45 +629,8 @@ static rewl_status create_impl(const rewl_config* cfgs, int32_t n, void* hip_str
             hi.lds = sweep_lds_bytes(c.model, c.L, hi.wpr, hi.WB, wpb);
             H->max_lds = std::max(H->max_lds, hi.lds);
         } else {
-            int want = H->tune.walkers_per_block > 0 ? H->tune.walkers_per_block : 4;
-            int G0 = 1;
-            while (G0 * 2 <= std::min(want, std::min(8, hi.m))) G0 *= 2;
-            // Walkers per block, count placement and site-map size: the choice that
-            // keeps the most of this instance's walkers resident at once (fewest
-            // rounds of blocks over the GPU's CUs), then the largest map (fewest
-            // shared entries), then the counts in LDS.
-            struct Choice { int G, mapn; bool hg; size_t lds; int64_t rounds; };
-            Choice best{0, 0, false, 0, INT64_MAX};
-            std::vector<bool> places;
-            if (H->tune.table_placement != REWL_TABLE_DEVICE) places.push_back(false);
-            if (H->tune.table_placement != REWL_TABLE_LDS) places.push_back(true);
-            std::vector<int> maps;
-            if (H->tune.map_log2 > 0) maps.push_back(wave_map_entries(hi.N, H->tune.map_log2));
-            else
-                for (int lg = 12; lg >= 9; --lg) {
-                    const int mn = wave_map_entries(hi.N, lg);
-                    if (maps.empty() || mn < maps.back()) maps.push_back(mn);
-                }
-            auto search = [&](const std::vector<bool>& pl) {
-                for (int mapn : maps)
-                    for (bool hg : pl) {
-                        int G = G0;
-                        while (G > 1 && wave_lds_bytes(c.model, c.L, hi.WB, G, hg, mapn) > (size_t)lds_limit)
-                            G /= 2;
-                        const size_t lds = wave_lds_bytes(c.model, c.L, hi.WB, G, hg, mapn);
-                        if (lds > (size_t)lds_limit) continue;
-                        const int64_t per_cu =
-                            std::max<int64_t>(1, std::min<int64_t>((int64_t)lds_limit / (int64_t)lds, wave_cap / G));
-                        const int64_t resident = per_cu * G * n_cu;
-                        const int64_t rounds = (hi.S + resident - 1) / resident;
-                        // candidates come largest map first, LDS before device memory
-                        if (rounds < best.rounds) best = Choice{G, mapn, hg, lds, rounds};
-                    }
-            };
-            search(places);
-            // counts asked for in LDS that do not fit there go to device memory
-            if (best.G == 0) search({true});
-            if (best.G == 0)
+            WavePlan best;
+            if (!plan_wave(c.model, c.L, hi.N, hi.WB, hi.m, hi.S, H->tune, lds_limit, n_cu, wave_cap, &best))
                 return bail(fail(REWL_E_INVALID, "instance " + std::to_string(i) + ": one walker's tables exceed LDS"));
             hi.placement = best.hg ? REWL_TABLE_DEVICE : REWL_TABLE_LDS;
             hi.wpb = best.G;
