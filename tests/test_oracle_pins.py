@@ -359,6 +359,30 @@ def test_rewl_converges_to_exact_ising_L8(golden):
     assert err.max() < 0.08
 
 
+def test_error_falls_with_walkers_per_window(golden):
+    """Sec. IV.B (`fig:scaling`): averaging the m walkers of a window at every merge
+    lowers the error of ln g at least as fast as m^-1/2.  Ising L=8 (4 windows,
+    ln f -> 2^-16), six seeds for each of m = 1, 4, 16: the RMS over seeds of the RMS
+    error against the exact DOS must shrink by at least 2/1.3 from m to 4 m (measured:
+    0.145 -> 0.045 -> 0.0185; a merge that keeps walker 0's table instead of the mean
+    gives 0.145 -> 0.090 -> 0.101 and fails)."""
+    exact = X.ln_g(golden.counts("ising_q2_L8_counts.txt"))
+    ok = np.isfinite(exact)
+
+    def rms(m):
+        errs = []
+        for seed in range(1, 7):
+            c = O.make_config("ising", L=8, n_windows=4, m=m, kfinal=16, seed=seed)
+            sim = O.Sim(c)
+            assert sim.run(200000)
+            out, _ = O.concat(c, O.mask_rule(c), sim.pieces())
+            errs.append(np.sqrt(np.mean((out[ok] - exact[ok]) ** 2)))
+        return float(np.sqrt(np.mean(np.square(errs))))
+
+    r1, r4, r16 = rms(1), rms(4), rms(16)
+    assert r4 <= 1.3 * r1 / 2 and r16 <= 1.3 * r4 / 2, (r1, r4, r16)
+
+
 def test_rewl_converges_to_exact_potts_q3_L4(golden):
     exact = X.ln_g(golden.counts("potts_q3_L4_counts.txt"))
     c = O.make_config("potts", q=3, L=4, n_windows=3, m=8, kfinal=18, X=5000, seed=2)
