@@ -113,9 +113,9 @@ typedef struct {
     int32_t lds_target_kb;      /* LANE: cap on a tile's LDS (sets walkers per block and
                                    so blocks per CU); 0 = the device limit               */
     int32_t autotune;           /* 1: time candidate variants, LDS targets, the
-                                   persistent lane sweep and table placements on the
-                                   real batch for two intervals at creation, keep the
-                                   fastest                                               */
+                                   persistent lane sweep, table placements and site-map
+                                   sizes on the real batch for two intervals at
+                                   creation, keep the fastest                          */
     int32_t guard_band_log2;    /* guard band of the fast acceptance test, 2^v:
                                    0 = 2^-40 (the default); -40..-2 widen it.  Every
                                    decision stays exact either way; a wider band only
